@@ -1,0 +1,204 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) implementation of the Galilean-
+ * invariant preconditioned cascaded central-moment D2Q9 lattice Boltzmann
+ * method (Hajabdollahi & Premnath, arXiv:1806.10251).
+ *
+ * One time step is one fused pass over the lattice: pull-streaming with the
+ * boundary links (eq. 2b; Sec. 6 boundary rules), macroscopic fields, the
+ * same-time-level density gradient, the local strain-rate estimate
+ * (eqs. 51-55), the extended-equilibrium GI corrections (eqs. 45-47) and the
+ * cascaded collision of Sec. 5 (eq. 2a), written to the second lattice.
+ *
+ * Conventions shared by every call:
+ *   - Every call returns an int status (LBM_OK or a negative LBM_E* code); on
+ *     failure lbm_last_error() returns a thread-local message.  Nothing throws
+ *     across the ABI.
+ *   - Host input arrays are copied during the call; the caller keeps them.
+ *     Output buffers are allocated by the caller.
+ *   - A context owns all device memory it uses; lbm_destroy frees it
+ *     (NULL is a no-op).
+ *   - Arrays of nodes are row-major [ny][nx]; node (i, j) sits at
+ *     x = i + 1/2, y = j + 1/2; the walls are half-way, at x in {0, nx} and
+ *     y in {0, ny}.  Population arrays are [9][ny][nx] in the velocity order
+ *     e = (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1) (-1,-1) (1,-1).
+ *   - "Device" pointers are HIP device addresses on the context's device.
+ *   - Work is queued on the context's stream (its own, or the one given to
+ *     lbm_set_stream); calls that return host data synchronise that stream.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;     /* one lattice; opaque */
+typedef struct lbm_batch lbm_batch; /* many independent lattices; opaque */
+
+enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,    /* invalid argument or configuration                 */
+  LBM_ENOMEM = -2,    /* device or host allocation failed                  */
+  LBM_EDEVICE = -3,   /* a HIP call failed                                 */
+  LBM_EUNSTABLE = -4, /* the fields became non-finite (divergence)         */
+  LBM_ESTATE = -5     /* call not valid in the current state               */
+};
+
+/* Side kinds (Sec. 6).  side[] is ordered W, E, S, N. */
+enum {
+  LBM_SIDE_PERIODIC = 0, /* both sides of an axis must be periodic          */
+  LBM_SIDE_WALL = 1,     /* stationary half-way bounce-back                 */
+  LBM_SIDE_LID = 2,      /* momentum-augmented half-way bounce-back, moving
+                            tangentially (+x on S/N, +y on W/E) at u_lid     */
+  LBM_SIDE_INLET = 3,    /* W only: moving-wall bounce-back with the
+                            parabolic profile 4 U y (H - y) / H^2            */
+  LBM_SIDE_OUTLET = 4    /* E only: convective condition on the velocity,
+                            density held at rho0 (see the design notes)      */
+};
+
+/* Population storage (all compute is FP32, except F64 which computes in FP64).
+ * Populations are stored as deviations f - w*rho0; BF16/FP16 store them
+ * multiplied by a power-of-two scale. */
+enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_BF16 = 2, LBM_STORE_F16 = 3 };
+
+typedef struct {
+  int32_t nx, ny;  /* nodes per row / per column, >= 2 each               */
+  int32_t side[4]; /* LBM_SIDE_* for W, E, S, N                            */
+} lbm_grid;
+
+typedef struct {
+  double nu;      /* kinematic viscosity; w4 = w5 = 1/(3 nu/gamma + 1/2),
+                     from nu = gamma/3 (1/w - 1/2) (Sec. 2, eq. 49)        */
+  double omega3;  /* bulk relaxation rate (eq. 49); 0 -> 1.0               */
+  double omega6, omega7, omega8; /* third/fourth-order rates; 0 -> 1.0    */
+  double gamma;   /* preconditioning parameter, 0 < gamma <= 1             */
+  double u_lid;   /* speed of LID sides                                    */
+  double u_in_max;/* peak of the INLET profile; also the OUTLET's U_max    */
+  double rho0;    /* reference density; 0 -> 1.0                          */
+  double fx, fy;  /* uniform body force (source moments of Sec. 3)         */
+  double storage_scale; /* BF16/FP16 scale (power of two); 0 -> default    */
+  int32_t storage;      /* LBM_STORE_*                                      */
+  int32_t gi_correct;   /* 1: Sec. 5 kernel; 0: eq. 4 kernel (uncorrected) */
+  int32_t drho_stencil; /* 0: isotropic FD (default); 1: central FD        */
+  int32_t check_every;  /* K >= 1: residual/mass reduction cadence (steps) */
+} lbm_params;
+
+/* Create a lattice at rest (f = w*rho0) on the current HIP device.
+ * solid_mask: ny*nx bytes, nonzero = solid node, NULL = all fluid; copied.
+ * Errors: LBM_EINVAL for sizes < 2, a periodic side facing a non-periodic
+ * one, INLET off W or OUTLET off E, gamma <= 0, nu <= 0, an unknown storage,
+ * check_every < 1, or solid nodes in the two columns next to an OUTLET;
+ * LBM_ENOMEM / LBM_EDEVICE from HIP. */
+int lbm_create(const lbm_grid* grid, const uint8_t* solid_mask, const lbm_params* params,
+               lbm_ctx** out);
+
+/* Re-initialise every fluid node to the equilibrium (Sec. 3 raw equilibria;
+ * central fourth order rho/9) at the given host fields (ny*nx doubles each;
+ * NULL -> rho0 / zero velocity).  Resets the step counter. */
+int lbm_init_fields(lbm_ctx* ctx, const double* rho, const double* ux, const double* uy);
+
+/* Same, from device arrays of ny*nx floats (e.g. a warm-start prediction
+ * already on the GPU).  NULL -> rho0 / zero velocity. */
+int lbm_init_fields_device(lbm_ctx* ctx, const float* rho, const float* ux, const float* uy);
+
+/* Queue all further work on hip_stream (a hipStream_t; NULL = the context's
+ * own stream).  The stream must outlive the context or a later call here. */
+int lbm_set_stream(lbm_ctx* ctx, void* hip_stream);
+
+/* Advance n >= 0 time steps (asynchronous on the stream).  Every step whose
+ * 1-based index is a multiple of check_every also reduces, in FP64, the
+ * steady-state residual and the mass. */
+int lbm_step(lbm_ctx* ctx, int64_t n);
+
+/* Residual of the last check step, sqrt(sum |u^{n+1}-u^n|^2 / sum |u^n|^2)
+ * over fluid nodes.  Synchronises.  LBM_ESTATE before the first check step;
+ * LBM_EUNSTABLE (and *r set) when it is not finite. */
+int lbm_residual(lbm_ctx* ctx, double* r);
+
+/* FP64 sum of rho over fluid nodes at the last check step.  Synchronises. */
+int lbm_mass(lbm_ctx* ctx, double* m);
+
+/* Number of fluid nodes whose 2x2 strain system was replaced by its gamma-
+ * free form (singular-system guard) at the last check step. */
+int lbm_guard_count(lbm_ctx* ctx, int64_t* n);
+
+/* Steps taken since the last initialisation. */
+int lbm_steps(lbm_ctx* ctx, int64_t* n);
+
+/* Macroscopic fields of the current state into caller-owned host arrays of
+ * ny*nx doubles (any may be NULL).  Solid nodes report 0.  Synchronises. */
+int lbm_fields(lbm_ctx* ctx, double* rho, double* ux, double* uy);
+
+/* Same into device arrays of ny*nx floats (asynchronous). */
+int lbm_fields_device(lbm_ctx* ctx, float* rho, float* ux, float* uy);
+
+/* Current post-collision populations f (not deviations), decoded to FP64,
+ * into a caller-owned host array of 9*ny*nx doubles.  Synchronises. */
+int lbm_populations(lbm_ctx* ctx, double* f);
+
+/* Checkpoint: raw storage lattice, outlet history and step counter. */
+int lbm_save(lbm_ctx* ctx, const char* path);
+int lbm_load(lbm_ctx* ctx, const char* path);
+
+/* Launch shape of the fused step: block of 64 x by threads, each thread
+ * holding `rows` lattice rows (the autotuner's knobs).  Supported pairs are
+ * listed by lbm_launch_shapes.  Rebuilds cached graphs. */
+int lbm_set_launch(lbm_ctx* ctx, int32_t by, int32_t rows);
+int lbm_get_launch(lbm_ctx* ctx, int32_t* by, int32_t* rows);
+/* Writes up to cap (by, rows) pairs into shapes[2*i], shapes[2*i+1]; returns
+ * the number of supported pairs. */
+int lbm_launch_shapes(int32_t* shapes, int32_t cap);
+
+/* Average device time of the fused step kernel over the last lbm_step call
+ * that was timed (set timing=1 first), in milliseconds. */
+int lbm_set_timing(lbm_ctx* ctx, int32_t timing);
+int lbm_last_step_ms(lbm_ctx* ctx, double* ms);
+
+void lbm_destroy(lbm_ctx* ctx);
+
+/* Thread-local description of the last failure on this thread. */
+const char* lbm_last_error(void);
+
+/* ---------------------------------------------------------------------- */
+/* Batch: n independent steady cases advanced together by one persistent  */
+/* kernel (a grid-wide barrier per time step; a case retires when its     */
+/* residual falls below tol at a check step).  Storage is FP32 deviations. */
+/* ---------------------------------------------------------------------- */
+
+/* grids[c], masks[c] (ny*nx bytes or NULL), params[c] for c < n.  All
+ * params must use LBM_STORE_F32 and the same check_every.  Inputs copied. */
+int lbm_batch_create(int32_t n, const lbm_grid* grids, const uint8_t* const* masks,
+                     const lbm_params* params, lbm_batch** out);
+
+/* Equilibrium initialisation of case c from host fields (NULL -> rest). */
+int lbm_batch_init_fields(lbm_batch* b, int32_t c, const double* rho, const double* ux,
+                          const double* uy);
+/* Same from device float arrays. */
+int lbm_batch_init_fields_device(lbm_batch* b, int32_t c, const float* rho, const float* ux,
+                                 const float* uy);
+
+int lbm_batch_set_stream(lbm_batch* b, void* hip_stream);
+
+/* Run until every case has residual < tol at a check step, or max_steps
+ * steps.  steps_per_case (n entries, may be NULL) receives the step at which
+ * each case retired (or max_steps).  Returns LBM_EUNSTABLE if some case
+ * diverged (that case retires with its step count negated). */
+int lbm_batch_run(lbm_batch* b, double tol, int64_t max_steps, int64_t* steps_per_case);
+
+/* Residual of case c at its last check step. */
+int lbm_batch_residual(lbm_batch* b, int32_t c, double* r);
+
+int lbm_batch_fields(lbm_batch* b, int32_t c, double* rho, double* ux, double* uy);
+
+/* Tile rows per work item and persistent grid size (0 = automatic). */
+int lbm_batch_set_launch(lbm_batch* b, int32_t rows_per_item, int32_t blocks);
+
+void lbm_batch_destroy(lbm_batch* b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

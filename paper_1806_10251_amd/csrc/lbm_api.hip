@@ -1,0 +1,805 @@
+// Host side of the single-lattice C ABI declared in include/lbm.h, plus the
+// small auxiliary kernels (partial-sum finalisation, equilibrium
+// initialisation, export).  The fused step kernels live in lbm_kernels.h and
+// are instantiated per storage type in lbm_step_<type>.hip.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_kernels.h"
+
+using namespace lbmk;
+
+namespace {
+
+// Fixed-order sum of the per-tile partials: out[0..3].
+__global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict__ partials,
+                                                       int n, double* __restrict__ out) {
+  __shared__ double s[4][256];
+  const int t = threadIdx.x;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = t; i < n; i += 256)
+    for (int c = 0; c < 4; ++c) a[c] += partials[(long long)i * 4 + c];
+  for (int c = 0; c < 4; ++c) s[c][t] = a[c];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h)
+      for (int c = 0; c < 4; ++c) s[c][t] += s[c][t + h];
+    __syncthreads();
+  }
+  if (t < 4) out[t] = s[t][0];
+}
+
+// Equilibrium initialisation from optional device fields (float); also
+// writes the velocity buffer and the outlet history.
+template <class S, class FT>
+__global__ __launch_bounds__(256) void init_kernel(typename S::T* __restrict__ fa,
+                                                   typename S::T* __restrict__ fb, Geom g,
+                                                   Consts<typename S::C> k,
+                                                   const uint8_t* __restrict__ solid,
+                                                   const FT* __restrict__ rho,
+                                                   const FT* __restrict__ ux,
+                                                   const FT* __restrict__ uy,
+                                                   typename S::C* __restrict__ ubuf,
+                                                   typename S::C* __restrict__ hist0,
+                                                   typename S::C* __restrict__ hist1) {
+  using C = typename S::C;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.plane) return;
+  const bool sol = solid && solid[i];
+  C drho = C(0), vx = C(0), vy = C(0);
+  if (!sol) {
+    if (rho) drho = C(rho[i]) - k.rho0;
+    if (ux) vx = C(ux[i]);
+    if (uy) vy = C(uy[i]);
+  }
+  C f[9];
+  equilibrium_dev<C>(drho, vx, vy, k, f);
+#pragma unroll
+  for (int a = 0; a < 9; ++a) {
+    const typename S::T v = S::enc(f[a], k.scale);
+    fa[a * g.plane + i] = v;
+    fb[a * g.plane + i] = v;
+  }
+  ubuf[i] = vx;
+  ubuf[g.plane + i] = vy;
+  const int x = int(i % g.nx), y = int(i / g.nx);
+  if (x == g.nx - 1) {
+    hist0[y] = vx;
+    hist0[g.ny + y] = vy;
+    hist1[y] = vx;
+    hist1[g.ny + y] = vy;
+  }
+}
+
+// Decode populations (full f) or macroscopic fields of the current lattice.
+template <class S>
+__global__ __launch_bounds__(256) void export_kernel(const typename S::T* __restrict__ fa, Geom g,
+                                                     Consts<typename S::C> k,
+                                                     const uint8_t* __restrict__ solid,
+                                                     double* __restrict__ pops,
+                                                     float* __restrict__ rho_o,
+                                                     float* __restrict__ ux_o,
+                                                     float* __restrict__ uy_o,
+                                                     double* __restrict__ rho_d,
+                                                     double* __restrict__ ux_d,
+                                                     double* __restrict__ uy_d) {
+  using C = typename S::C;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.plane) return;
+  C d[9];
+#pragma unroll
+  for (int a = 0; a < 9; ++a) d[a] = S::dec(fa[a * g.plane + i], k.inv_scale);
+  if (pops) {
+#pragma unroll
+    for (int a = 0; a < 9; ++a)
+      pops[a * g.plane + i] = double(d[a]) + double(w_of<C>(a)) * double(k.rho0);
+  }
+  const bool sol = solid && solid[i];
+  // post-collision moments: rho is unchanged by collision; the momentum has
+  // received F/gamma, so u = (sum e f~ - F/(2 gamma)) / rho
+  C drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
+  C jx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
+  C jy = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
+  if (k.force) {
+    jx -= C(0.5) * k.fx * k.ig;
+    jy -= C(0.5) * k.fy * k.ig;
+  }
+  const C rho = k.rho0 + drho;
+  const C vx = jx / rho, vy = jy / rho;
+  if (rho_o) rho_o[i] = sol ? 0.f : float(rho);
+  if (ux_o) ux_o[i] = sol ? 0.f : float(vx);
+  if (uy_o) uy_o[i] = sol ? 0.f : float(vy);
+  if (rho_d) rho_d[i] = sol ? 0.0 : double(k.rho0) + double(drho);
+  if (ux_d) ux_d[i] = sol ? 0.0 : double(vx);
+  if (uy_d) uy_d[i] = sol ? 0.0 : double(vy);
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHECK(expr)                                                              \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return fail(LBM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct Shape {
+  int by, rows;
+};
+constexpr Shape kShapes[] = {{4, 4}, {8, 2}, {8, 4}, {16, 1}, {16, 2}, {4, 2}};
+constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
+
+size_t storage_bytes(int storage) {
+  switch (storage) {
+    case LBM_STORE_F64: return 8;
+    case LBM_STORE_F32: return 4;
+    default: return 2;
+  }
+}
+
+}  // namespace
+
+struct lbm_ctx {
+  lbm_grid grid{};
+  lbm_params p{};
+  int device = 0;
+  hipStream_t own_stream = nullptr;
+  hipStream_t stream = nullptr;
+  size_t esize = 4;   // bytes per stored population
+  size_t csize = 4;   // bytes per compute value
+  void* lat[2] = {nullptr, nullptr};
+  uint8_t* d_solid = nullptr;  // nullptr when no solid node
+  std::vector<uint8_t> h_solid;
+  uint8_t* d_tile_fast = nullptr;
+  void* hist[2] = {nullptr, nullptr};
+  void* ubuf = nullptr;
+  double* partials = nullptr;
+  double* result = nullptr;
+  int cur = 0;
+  int64_t t = 0;
+  bool checked = false;
+  int by = 4, rows = 4;
+  int tiles_x = 0, tiles_y = 0, ntiles = 0, out_rows = 0;
+  size_t partial_cap = 0;
+  Consts<double> kd{};
+  Consts<float> kf{};
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  bool timing = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double last_ms = -1.0;
+};
+
+namespace {
+
+template <class C>
+const Consts<C>& consts_for(const lbm_ctx* c);
+template <>
+const Consts<double>& consts_for<double>(const lbm_ctx* c) { return c->kd; }
+template <>
+const Consts<float>& consts_for<float>(const lbm_ctx* c) { return c->kf; }
+
+template <class C>
+Consts<C> make_consts(const lbm_params& p, double scale) {
+  const double g = p.gamma;
+  const double w4 = 1.0 / (3.0 * p.nu / g + 0.5);
+  Consts<C> k{};
+  k.rho0 = C(p.rho0);
+  k.ig = C(1.0 / g);
+  k.third = C(p.gi_correct ? 3.0 / g - 1.0 / (g * g) : 2.0);
+  k.A = C(4.0 / (g * g) - 1.0 / g);
+  k.B = C(1.0 / (g * g) - 1.0 / g);
+  k.Cg = C(1.0 / g - 1.0);
+  k.h3 = C(1.0 / p.omega3 - 0.5);
+  k.h4 = C(1.0 / w4 - 0.5);
+  k.h5 = C(1.0 / w4 - 0.5);
+  k.a3 = C(2.0 / (3.0 * p.omega3));
+  k.a4 = C(2.0 / (3.0 * w4));
+  k.w3 = C(p.omega3);
+  k.w4 = C(w4);
+  k.w5 = C(w4);
+  k.w6 = C(p.omega6);
+  k.w7 = C(p.omega7);
+  k.w8 = C(p.omega8);
+  k.fx = C(p.fx);
+  k.fy = C(p.fy);
+  k.u_lid = C(p.u_lid);
+  k.u_in_max = C(p.u_in_max);
+  k.scale = C(scale);
+  k.inv_scale = C(1.0 / scale);
+  k.gi = p.gi_correct ? 1 : 0;
+  k.force = (p.fx != 0.0 || p.fy != 0.0) ? 1 : 0;
+  k.stencil = p.drho_stencil;
+  return k;
+}
+
+Geom make_geom(const lbm_ctx* c) {
+  Geom g{};
+  g.nx = c->grid.nx;
+  g.ny = c->grid.ny;
+  for (int s = 0; s < 4; ++s) g.side[s] = c->grid.side[s];
+  g.plane = (long long)g.nx * g.ny;
+  return g;
+}
+
+int validate(const lbm_grid* grid, const uint8_t* solid, const lbm_params* p) {
+  if (!grid || !p) return fail(LBM_EINVAL, "null grid or params");
+  if (grid->nx < 2 || grid->ny < 2) return fail(LBM_EINVAL, "nx and ny must be >= 2");
+  if ((long long)grid->nx * grid->ny > (1LL << 31))
+    return fail(LBM_EINVAL, "lattice too large (more than 2^31 nodes)");
+  for (int s = 0; s < 4; ++s)
+    if (grid->side[s] < LBM_SIDE_PERIODIC || grid->side[s] > LBM_SIDE_OUTLET)
+      return fail(LBM_EINVAL, "unknown side kind");
+  if ((grid->side[0] == LBM_SIDE_PERIODIC) != (grid->side[1] == LBM_SIDE_PERIODIC) ||
+      (grid->side[2] == LBM_SIDE_PERIODIC) != (grid->side[3] == LBM_SIDE_PERIODIC))
+    return fail(LBM_EINVAL, "a periodic side must face a periodic side");
+  for (int s = 0; s < 4; ++s) {
+    if (grid->side[s] == LBM_SIDE_INLET && s != 0) return fail(LBM_EINVAL, "INLET only on W");
+    if (grid->side[s] == LBM_SIDE_OUTLET && s != 1) return fail(LBM_EINVAL, "OUTLET only on E");
+  }
+  if (!(p->gamma > 0.0) || !(p->gamma <= 1.0)) return fail(LBM_EINVAL, "gamma must be in (0, 1]");
+  if (!(p->nu > 0.0)) return fail(LBM_EINVAL, "nu must be > 0");
+  if (p->storage < LBM_STORE_F64 || p->storage > LBM_STORE_F16)
+    return fail(LBM_EINVAL, "unknown storage");
+  if (p->check_every < 1) return fail(LBM_EINVAL, "check_every must be >= 1");
+  if (!(p->omega3 >= 0 && p->omega3 < 2) || !(p->omega6 >= 0 && p->omega6 < 2) ||
+      !(p->omega7 >= 0 && p->omega7 < 2) || !(p->omega8 >= 0 && p->omega8 < 2))
+    return fail(LBM_EINVAL, "omega3/6/7/8 must be in (0, 2) (0 selects 1.0)");
+  if (grid->side[1] == LBM_SIDE_OUTLET && solid) {
+    for (int j = 0; j < grid->ny; ++j)
+      if (solid[(size_t)j * grid->nx + grid->nx - 1] || solid[(size_t)j * grid->nx + grid->nx - 2])
+        return fail(LBM_EINVAL, "solid nodes next to an OUTLET side");
+  }
+  return LBM_OK;
+}
+
+// A tile is "fast" when its region grown by one node (the pull sources) lies
+// inside the lattice and holds no solid node.
+void compute_tile_flags(const lbm_ctx* c, std::vector<uint8_t>& flags) {
+  const int nx = c->grid.nx, ny = c->grid.ny;
+  flags.assign(c->ntiles, 0);
+  const int rr = c->by * c->rows;
+  for (int t = 0; t < c->ntiles; ++t) {
+    const int tx = t % c->tiles_x, ty = t / c->tiles_x;
+    const int x0 = tx * kOutX - 2, x1 = tx * kOutX - 1 + kLanes;  // inclusive
+    const int y0 = ty * c->out_rows - 2, y1 = ty * c->out_rows - 1 + rr;
+    if (x0 < 0 || y0 < 0 || x1 >= nx || y1 >= ny) continue;
+    bool ok = true;
+    if (!c->h_solid.empty())
+      for (int y = y0; y <= y1 && ok; ++y)
+        for (int x = x0; x <= x1; ++x)
+          if (c->h_solid[(size_t)y * nx + x]) {
+            ok = false;
+            break;
+          }
+    flags[t] = ok ? 1 : 0;
+  }
+}
+
+int configure_tiles(lbm_ctx* c) {
+  const int rr = c->by * c->rows;
+  c->out_rows = rr - 2;
+  c->tiles_x = (c->grid.nx + kOutX - 1) / kOutX;
+  c->tiles_y = (c->grid.ny + c->out_rows - 1) / c->out_rows;
+  c->ntiles = c->tiles_x * c->tiles_y;
+  std::vector<uint8_t> flags;
+  compute_tile_flags(c, flags);
+  if (c->d_tile_fast) HIPCHECK(hipFree(c->d_tile_fast));
+  c->d_tile_fast = nullptr;
+  HIPCHECK(hipMalloc(&c->d_tile_fast, c->ntiles));
+  HIPCHECK(hipMemcpy(c->d_tile_fast, flags.data(), c->ntiles, hipMemcpyHostToDevice));
+  if ((size_t)c->ntiles > c->partial_cap) {
+    if (c->partials) HIPCHECK(hipFree(c->partials));
+    c->partials = nullptr;
+    HIPCHECK(hipMalloc(&c->partials, (size_t)c->ntiles * 4 * sizeof(double)));
+    c->partial_cap = c->ntiles;
+  }
+  for (int i = 0; i < 2; ++i)
+    if (c->graph[i]) {
+      hipGraphExecDestroy(c->graph[i]);
+      c->graph[i] = nullptr;
+    }
+  return LBM_OK;
+}
+
+// Queue one step (flavor by its 1-based index), then swap lattices.
+void enqueue_step(lbm_ctx* c, hipStream_t st) {
+  const int64_t idx = c->t + 1;
+  const int K = c->p.check_every;
+  int flavor = kPlain;
+  if (idx % K == 0) flavor = kCheck;
+  else if (K >= 2 && idx % K == K - 1) flavor = kStore;
+  StepArgs a{};
+  a.g = make_geom(c);
+  a.tiles_x = c->tiles_x;
+  a.ntiles = c->ntiles;
+  a.out_rows = c->out_rows;
+  a.solid = c->d_solid;
+  a.tile_fast = c->d_tile_fast;
+  a.hist_in = c->hist[c->cur];
+  a.hist_out = c->hist[c->cur ^ 1];
+  a.ubuf = c->ubuf;
+  a.partials = c->partials;
+  const void* src = c->lat[c->cur];
+  void* dst = c->lat[c->cur ^ 1];
+  switch (c->p.storage) {
+    case LBM_STORE_F64:
+      launch_step_f64(c->by, c->rows, flavor, src, dst, a, c->kd, c->ntiles, st);
+      break;
+    case LBM_STORE_F32:
+      launch_step_f32(c->by, c->rows, flavor, src, dst, a, c->kf, c->ntiles, st);
+      break;
+    case LBM_STORE_BF16:
+      launch_step_bf16(c->by, c->rows, flavor, src, dst, a, c->kf, c->ntiles, st);
+      break;
+    default:
+      launch_step_f16(c->by, c->rows, flavor, src, dst, a, c->kf, c->ntiles, st);
+      break;
+  }
+  if (flavor == kCheck) {
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, st, c->partials, c->ntiles,
+                       c->result);
+    c->checked = true;
+  }
+  c->cur ^= 1;
+  c->t = idx;
+}
+
+template <class S, class FT>
+void launch_init(lbm_ctx* c, const FT* rho, const FT* ux, const FT* uy) {
+  using C = typename S::C;
+  using T = typename S::T;
+  Geom g = make_geom(c);
+  const int blocks = int((g.plane + 255) / 256);
+  hipLaunchKernelGGL((init_kernel<S, FT>), dim3(blocks), dim3(256), 0, c->stream, (T*)c->lat[0],
+                     (T*)c->lat[1], g, consts_for<C>(c), c->d_solid, rho, ux, uy, (C*)c->ubuf,
+                     (C*)c->hist[0], (C*)c->hist[1]);
+}
+
+template <class FT>
+int init_common(lbm_ctx* c, const FT* rho, const FT* ux, const FT* uy) {
+  switch (c->p.storage) {
+    case LBM_STORE_F64: launch_init<StoreF64, FT>(c, rho, ux, uy); break;
+    case LBM_STORE_F32: launch_init<StoreF32, FT>(c, rho, ux, uy); break;
+    case LBM_STORE_BF16: launch_init<StoreBF16, FT>(c, rho, ux, uy); break;
+    default: launch_init<StoreF16, FT>(c, rho, ux, uy); break;
+  }
+  HIPCHECK(hipGetLastError());
+  c->cur = 0;
+  c->t = 0;
+  c->checked = false;
+  for (int i = 0; i < 2; ++i)
+    if (c->graph[i]) {
+      hipGraphExecDestroy(c->graph[i]);
+      c->graph[i] = nullptr;
+    }
+  return LBM_OK;
+}
+
+int export_common(lbm_ctx* c, double* pops, float* ro, float* uxo, float* uyo, double* rd,
+                  double* uxd, double* uyd) {
+  Geom g = make_geom(c);
+  const int blocks = int((g.plane + 255) / 256);
+  const void* src = c->lat[c->cur];
+  switch (c->p.storage) {
+    case LBM_STORE_F64:
+      hipLaunchKernelGGL(export_kernel<StoreF64>, dim3(blocks), dim3(256), 0, c->stream,
+                         (const double*)src, g, c->kd, c->d_solid, pops, ro, uxo, uyo, rd, uxd,
+                         uyd);
+      break;
+    case LBM_STORE_F32:
+      hipLaunchKernelGGL(export_kernel<StoreF32>, dim3(blocks), dim3(256), 0, c->stream,
+                         (const float*)src, g, c->kf, c->d_solid, pops, ro, uxo, uyo, rd, uxd,
+                         uyd);
+      break;
+    case LBM_STORE_BF16:
+      hipLaunchKernelGGL(export_kernel<StoreBF16>, dim3(blocks), dim3(256), 0, c->stream,
+                         (const uint16_t*)src, g, c->kf, c->d_solid, pops, ro, uxo, uyo, rd, uxd,
+                         uyd);
+      break;
+    default:
+      hipLaunchKernelGGL(export_kernel<StoreF16>, dim3(blocks), dim3(256), 0, c->stream,
+                         (const _Float16*)src, g, c->kf, c->d_solid, pops, ro, uxo, uyo, rd,
+                         uxd, uyd);
+      break;
+  }
+  HIPCHECK(hipGetLastError());
+  return LBM_OK;
+}
+
+void free_ctx(lbm_ctx* c) {
+  if (!c) return;
+  for (int i = 0; i < 2; ++i) {
+    if (c->graph[i]) hipGraphExecDestroy(c->graph[i]);
+    if (c->lat[i]) hipFree(c->lat[i]);
+    if (c->hist[i]) hipFree(c->hist[i]);
+  }
+  if (c->d_solid) hipFree(c->d_solid);
+  if (c->d_tile_fast) hipFree(c->d_tile_fast);
+  if (c->ubuf) hipFree(c->ubuf);
+  if (c->partials) hipFree(c->partials);
+  if (c->result) hipFree(c->result);
+  if (c->ev0) hipEventDestroy(c->ev0);
+  if (c->ev1) hipEventDestroy(c->ev1);
+  if (c->own_stream) hipStreamDestroy(c->own_stream);
+  delete c;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_last_error(void) { return g_err.c_str(); }
+
+int lbm_launch_shapes(int32_t* shapes, int32_t cap) {
+  for (int i = 0; i < kNumShapes && i < cap; ++i) {
+    shapes[2 * i] = kShapes[i].by;
+    shapes[2 * i + 1] = kShapes[i].rows;
+  }
+  return kNumShapes;
+}
+
+int lbm_create(const lbm_grid* grid, const uint8_t* solid_mask, const lbm_params* params,
+               lbm_ctx** out) {
+  if (!out) return fail(LBM_EINVAL, "null output pointer");
+  *out = nullptr;
+  int rc = validate(grid, solid_mask, params);
+  if (rc) return rc;
+  lbm_ctx* c = new (std::nothrow) lbm_ctx();
+  if (!c) return fail(LBM_ENOMEM, "host allocation failed");
+  c->grid = *grid;
+  c->p = *params;
+  if (c->p.omega3 == 0) c->p.omega3 = 1.0;
+  if (c->p.omega6 == 0) c->p.omega6 = 1.0;
+  if (c->p.omega7 == 0) c->p.omega7 = 1.0;
+  if (c->p.omega8 == 0) c->p.omega8 = 1.0;
+  if (c->p.rho0 == 0) c->p.rho0 = 1.0;
+  double scale = 1.0;
+  if (c->p.storage == LBM_STORE_BF16 || c->p.storage == LBM_STORE_F16) {
+    scale = c->p.storage_scale > 0 ? c->p.storage_scale
+                                   : (c->p.storage == LBM_STORE_F16 ? 4096.0 : 1.0);
+    int e;
+    if (std::frexp(scale, &e) != 0.5) {
+      free_ctx(c);
+      return fail(LBM_EINVAL, "storage_scale must be a power of two");
+    }
+  }
+  c->kd = make_consts<double>(c->p, scale);
+  c->kf = make_consts<float>(c->p, scale);
+  c->esize = storage_bytes(c->p.storage);
+  c->csize = c->p.storage == LBM_STORE_F64 ? 8 : 4;
+  if (c->p.storage == LBM_STORE_F64) {
+    c->by = 8;
+    c->rows = 2;
+  }
+  auto dev = [&](hipError_t e, const char* what) {
+    if (e != hipSuccess) {
+      g_err = std::string(what) + ": " + hipGetErrorString(e);
+      return false;
+    }
+    return true;
+  };
+  const size_t n = (size_t)grid->nx * grid->ny;
+  bool ok = dev(hipGetDevice(&c->device), "hipGetDevice") &&
+            dev(hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking), "hipStreamCreate");
+  c->stream = c->own_stream;
+  for (int i = 0; ok && i < 2; ++i) {
+    ok = dev(hipMalloc(&c->lat[i], 9 * n * c->esize), "hipMalloc lattice") &&
+         dev(hipMalloc(&c->hist[i], 2 * (size_t)grid->ny * c->csize), "hipMalloc history");
+  }
+  ok = ok && dev(hipMalloc(&c->ubuf, 2 * n * c->csize), "hipMalloc velocity") &&
+       dev(hipMalloc(&c->result, 4 * sizeof(double)), "hipMalloc result") &&
+       dev(hipEventCreate(&c->ev0), "hipEventCreate") &&
+       dev(hipEventCreate(&c->ev1), "hipEventCreate");
+  if (ok && solid_mask) {
+    bool any = false;
+    for (size_t i = 0; i < n; ++i) any |= solid_mask[i] != 0;
+    if (any) {
+      c->h_solid.assign(solid_mask, solid_mask + n);
+      for (auto& v : c->h_solid) v = v ? 1 : 0;
+      ok = dev(hipMalloc(&c->d_solid, n), "hipMalloc mask") &&
+           dev(hipMemcpy(c->d_solid, c->h_solid.data(), n, hipMemcpyHostToDevice), "copy mask");
+    }
+  }
+  if (!ok) {
+    free_ctx(c);
+    return LBM_EDEVICE;
+  }
+  rc = configure_tiles(c);
+  if (!rc) rc = init_common<double>(c, nullptr, nullptr, nullptr);
+  if (!rc) {
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) rc = fail(LBM_EDEVICE, hipGetErrorString(e));
+  }
+  if (rc) {
+    free_ctx(c);
+    return rc;
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx* c) {
+  if (!c) return;
+  if (c->stream) hipStreamSynchronize(c->stream);
+  free_ctx(c);
+}
+
+int lbm_set_stream(lbm_ctx* c, void* s) {
+  if (!c) return fail(LBM_EINVAL, "null context");
+  HIPCHECK(hipStreamSynchronize(c->stream));
+  c->stream = s ? (hipStream_t)s : c->own_stream;
+  return LBM_OK;
+}
+
+int lbm_init_fields(lbm_ctx* c, const double* rho, const double* ux, const double* uy) {
+  if (!c) return fail(LBM_EINVAL, "null context");
+  const size_t n = (size_t)c->grid.nx * c->grid.ny;
+  double* tmp[3] = {nullptr, nullptr, nullptr};
+  const double* src[3] = {rho, ux, uy};
+  int rc = LBM_OK;
+  for (int i = 0; i < 3 && rc == LBM_OK; ++i) {
+    if (!src[i]) continue;
+    if (hipMalloc(&tmp[i], n * sizeof(double)) != hipSuccess ||
+        hipMemcpy(tmp[i], src[i], n * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+      rc = fail(LBM_EDEVICE, "upload of initial fields failed");
+  }
+  if (rc == LBM_OK) rc = init_common<double>(c, tmp[0], tmp[1], tmp[2]);
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (rc == LBM_OK && e != hipSuccess) rc = fail(LBM_EDEVICE, hipGetErrorString(e));
+  for (int i = 0; i < 3; ++i)
+    if (tmp[i]) hipFree(tmp[i]);
+  return rc;
+}
+
+int lbm_init_fields_device(lbm_ctx* c, const float* rho, const float* ux, const float* uy) {
+  if (!c) return fail(LBM_EINVAL, "null context");
+  return init_common<float>(c, rho, ux, uy);
+}
+
+int lbm_step(lbm_ctx* c, int64_t n) {
+  if (!c) return fail(LBM_EINVAL, "null context");
+  if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
+  if (n == 0) return LBM_OK;
+  const int K = c->p.check_every;
+  hipStream_t st = c->stream;
+  if (c->timing) HIPCHECK(hipEventRecord(c->ev0, st));
+  int64_t left = n;
+  // replay a captured graph of K steps for every aligned block of K steps
+  while (left > 0) {
+    if (c->t % K == 0 && left >= K && K >= 4) {
+      const int par = c->cur;
+      if (!c->graph[par]) {
+        hipGraph_t gr = nullptr;
+        const int64_t t0 = c->t;
+        const int cur0 = c->cur;
+        const bool chk0 = c->checked;
+        HIPCHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        for (int i = 0; i < K; ++i) enqueue_step(c, st);
+        hipError_t e = hipStreamEndCapture(st, &gr);
+        c->t = t0;
+        c->cur = cur0;
+        c->checked = chk0;
+        if (e != hipSuccess) return fail(LBM_EDEVICE, hipGetErrorString(e));
+        e = hipGraphInstantiate(&c->graph[par], gr, nullptr, nullptr, 0);
+        hipGraphDestroy(gr);
+        if (e != hipSuccess) {
+          c->graph[par] = nullptr;
+          return fail(LBM_EDEVICE, hipGetErrorString(e));
+        }
+      }
+      HIPCHECK(hipGraphLaunch(c->graph[par], st));
+      c->t += K;
+      if (K % 2) c->cur ^= 1;
+      c->checked = true;
+      left -= K;
+    } else {
+      enqueue_step(c, st);
+      --left;
+    }
+  }
+  HIPCHECK(hipGetLastError());
+  if (c->timing) {
+    HIPCHECK(hipEventRecord(c->ev1, st));
+    HIPCHECK(hipEventSynchronize(c->ev1));
+    float ms = 0.f;
+    HIPCHECK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    c->last_ms = double(ms) / double(n);
+  }
+  return LBM_OK;
+}
+
+int lbm_set_timing(lbm_ctx* c, int32_t timing) {
+  if (!c) return fail(LBM_EINVAL, "null context");
+  c->timing = timing != 0;
+  return LBM_OK;
+}
+
+int lbm_last_step_ms(lbm_ctx* c, double* ms) {
+  if (!c || !ms) return fail(LBM_EINVAL, "null argument");
+  if (c->last_ms < 0) return fail(LBM_ESTATE, "no timed step yet");
+  *ms = c->last_ms;
+  return LBM_OK;
+}
+
+static int read_result(lbm_ctx* c, double r[4]) {
+  if (!c->checked) return fail(LBM_ESTATE, "no check step has run yet");
+  HIPCHECK(hipStreamSynchronize(c->stream));
+  HIPCHECK(hipMemcpy(r, c->result, 4 * sizeof(double), hipMemcpyDeviceToHost));
+  return LBM_OK;
+}
+
+int lbm_residual(lbm_ctx* c, double* r) {
+  if (!c || !r) return fail(LBM_EINVAL, "null argument");
+  double v[4];
+  int rc = read_result(c, v);
+  if (rc) return rc;
+  if (!std::isfinite(v[0]) || !std::isfinite(v[1])) {
+    *r = NAN;
+    return fail(LBM_EUNSTABLE, "residual is not finite");
+  }
+  *r = v[1] > 0 ? std::sqrt(v[0] / v[1]) : (v[0] > 0 ? INFINITY : 0.0);
+  return LBM_OK;
+}
+
+int lbm_mass(lbm_ctx* c, double* m) {
+  if (!c || !m) return fail(LBM_EINVAL, "null argument");
+  double v[4];
+  int rc = read_result(c, v);
+  if (rc) return rc;
+  size_t fluid = (size_t)c->grid.nx * c->grid.ny;
+  if (!c->h_solid.empty()) {
+    fluid = 0;
+    for (auto s : c->h_solid) fluid += s == 0;
+  }
+  *m = double(fluid) * c->p.rho0 + v[2];
+  if (!std::isfinite(*m)) return fail(LBM_EUNSTABLE, "mass is not finite");
+  return LBM_OK;
+}
+
+int lbm_guard_count(lbm_ctx* c, int64_t* n) {
+  if (!c || !n) return fail(LBM_EINVAL, "null argument");
+  double v[4];
+  int rc = read_result(c, v);
+  if (rc) return rc;
+  *n = (int64_t)v[3];
+  return LBM_OK;
+}
+
+int lbm_steps(lbm_ctx* c, int64_t* n) {
+  if (!c || !n) return fail(LBM_EINVAL, "null argument");
+  *n = c->t;
+  return LBM_OK;
+}
+
+int lbm_fields(lbm_ctx* c, double* rho, double* ux, double* uy) {
+  if (!c) return fail(LBM_EINVAL, "null context");
+  const size_t n = (size_t)c->grid.nx * c->grid.ny;
+  double* d = nullptr;
+  HIPCHECK(hipMalloc(&d, 3 * n * sizeof(double)));
+  int rc = export_common(c, nullptr, nullptr, nullptr, nullptr, d, d + n, d + 2 * n);
+  if (rc == LBM_OK) {
+    hipError_t e = hipStreamSynchronize(c->stream);
+    double* h[3] = {rho, ux, uy};
+    for (int i = 0; i < 3 && e == hipSuccess; ++i)
+      if (h[i]) e = hipMemcpy(h[i], d + i * n, n * sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) rc = fail(LBM_EDEVICE, hipGetErrorString(e));
+  }
+  hipFree(d);
+  return rc;
+}
+
+int lbm_fields_device(lbm_ctx* c, float* rho, float* ux, float* uy) {
+  if (!c) return fail(LBM_EINVAL, "null context");
+  return export_common(c, nullptr, rho, ux, uy, nullptr, nullptr, nullptr);
+}
+
+int lbm_populations(lbm_ctx* c, double* f) {
+  if (!c || !f) return fail(LBM_EINVAL, "null argument");
+  const size_t n = (size_t)c->grid.nx * c->grid.ny;
+  double* d = nullptr;
+  HIPCHECK(hipMalloc(&d, 9 * n * sizeof(double)));
+  int rc = export_common(c, d, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+  if (rc == LBM_OK) {
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = hipMemcpy(f, d, 9 * n * sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) rc = fail(LBM_EDEVICE, hipGetErrorString(e));
+  }
+  hipFree(d);
+  return rc;
+}
+
+static const char kMagic[8] = {'L', 'B', 'M', 'C', 'K', 'P', 'T', '1'};
+
+int lbm_save(lbm_ctx* c, const char* path) {
+  if (!c || !path) return fail(LBM_EINVAL, "null argument");
+  HIPCHECK(hipStreamSynchronize(c->stream));
+  const size_t n = (size_t)c->grid.nx * c->grid.ny;
+  std::vector<char> lat(9 * n * c->esize), hist(2 * (size_t)c->grid.ny * c->csize);
+  HIPCHECK(hipMemcpy(lat.data(), c->lat[c->cur], lat.size(), hipMemcpyDeviceToHost));
+  HIPCHECK(hipMemcpy(hist.data(), c->hist[c->cur], hist.size(), hipMemcpyDeviceToHost));
+  std::vector<char> ub(2 * n * c->csize);
+  HIPCHECK(hipMemcpy(ub.data(), c->ubuf, ub.size(), hipMemcpyDeviceToHost));
+  FILE* fp = std::fopen(path, "wb");
+  if (!fp) return fail(LBM_EINVAL, std::string("cannot open ") + path);
+  int32_t hdr[8] = {c->grid.nx, c->grid.ny, c->p.storage, (int32_t)c->esize, 0, 0, 0, 0};
+  int64_t t = c->t;
+  bool ok = std::fwrite(kMagic, 1, 8, fp) == 8 && std::fwrite(hdr, sizeof hdr, 1, fp) == 1 &&
+            std::fwrite(&t, sizeof t, 1, fp) == 1 &&
+            std::fwrite(lat.data(), 1, lat.size(), fp) == lat.size() &&
+            std::fwrite(hist.data(), 1, hist.size(), fp) == hist.size() &&
+            std::fwrite(ub.data(), 1, ub.size(), fp) == ub.size();
+  ok = (std::fclose(fp) == 0) && ok;
+  return ok ? LBM_OK : fail(LBM_EDEVICE, "write failed");
+}
+
+int lbm_load(lbm_ctx* c, const char* path) {
+  if (!c || !path) return fail(LBM_EINVAL, "null argument");
+  FILE* fp = std::fopen(path, "rb");
+  if (!fp) return fail(LBM_EINVAL, std::string("cannot open ") + path);
+  char mg[8];
+  int32_t hdr[8];
+  int64_t t;
+  const size_t n = (size_t)c->grid.nx * c->grid.ny;
+  std::vector<char> lat(9 * n * c->esize), hist(2 * (size_t)c->grid.ny * c->csize),
+      ub(2 * n * c->csize);
+  bool ok = std::fread(mg, 1, 8, fp) == 8 && std::memcmp(mg, kMagic, 8) == 0 &&
+            std::fread(hdr, sizeof hdr, 1, fp) == 1 && hdr[0] == c->grid.nx &&
+            hdr[1] == c->grid.ny && hdr[2] == c->p.storage && std::fread(&t, sizeof t, 1, fp) == 1 &&
+            std::fread(lat.data(), 1, lat.size(), fp) == lat.size() &&
+            std::fread(hist.data(), 1, hist.size(), fp) == hist.size() &&
+            std::fread(ub.data(), 1, ub.size(), fp) == ub.size();
+  std::fclose(fp);
+  if (!ok) return fail(LBM_EINVAL, "checkpoint does not match this lattice");
+  HIPCHECK(hipStreamSynchronize(c->stream));
+  HIPCHECK(hipMemcpy(c->lat[0], lat.data(), lat.size(), hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(c->lat[1], lat.data(), lat.size(), hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(c->hist[0], hist.data(), hist.size(), hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(c->hist[1], hist.data(), hist.size(), hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(c->ubuf, ub.data(), ub.size(), hipMemcpyHostToDevice));
+  c->cur = 0;
+  c->t = t;
+  c->checked = false;
+  for (int i = 0; i < 2; ++i)
+    if (c->graph[i]) {
+      hipGraphExecDestroy(c->graph[i]);
+      c->graph[i] = nullptr;
+    }
+  return LBM_OK;
+}
+
+int lbm_set_launch(lbm_ctx* c, int32_t by, int32_t rows) {
+  if (!c) return fail(LBM_EINVAL, "null context");
+  bool known = false;
+  for (int i = 0; i < kNumShapes; ++i) known |= kShapes[i].by == by && kShapes[i].rows == rows;
+  if (!known) return fail(LBM_EINVAL, "unsupported launch shape");
+  HIPCHECK(hipStreamSynchronize(c->stream));
+  c->by = by;
+  c->rows = rows;
+  return configure_tiles(c);
+}
+
+int lbm_get_launch(lbm_ctx* c, int32_t* by, int32_t* rows) {
+  if (!c || !by || !rows) return fail(LBM_EINVAL, "null argument");
+  *by = c->by;
+  *rows = c->rows;
+  return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,370 @@
+// Device-side building blocks of the fused D2Q9 step for gfx950:
+// storage codecs, the equilibrium, the GI-corrected preconditioned cascaded
+// collision and the pull with boundary links.  Shared by the single-lattice
+// kernel (lbm_step.hip) and the persistent batch kernel (lbm_batch.hip).
+//
+// Populations are held as deviations d_a = f_a - w_a rho0 throughout, so the
+// large rest part never enters a rounding step; every moment below is the
+// moment of the deviation plus the analytically known moment of w rho0.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbmk {
+
+enum : int { kPeriodic = 0, kWall = 1, kLid = 2, kInlet = 3, kOutlet = 4 };
+enum : int { kW = 0, kE = 1, kS = 2, kN = 3 };
+
+// D2Q9 velocity set, order (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1) (-1,-1) (1,-1).
+__host__ __device__ constexpr int ex_of(int a) {
+  return a == 1 || a == 5 || a == 8 ? 1 : (a == 3 || a == 6 || a == 7 ? -1 : 0);
+}
+__host__ __device__ constexpr int ey_of(int a) {
+  return a == 2 || a == 5 || a == 6 ? 1 : (a == 4 || a == 7 || a == 8 ? -1 : 0);
+}
+__host__ __device__ constexpr int opp_of(int a) {
+  return a == 0 ? 0 : (a <= 4 ? ((a + 1) % 4) + 1 : ((a - 3) % 4) + 5);
+}
+template <class C>
+__host__ __device__ constexpr C w_of(int a) {
+  return a == 0 ? C(4) / C(9) : (a <= 4 ? C(1) / C(9) : C(1) / C(36));
+}
+
+// ---------------------------------------------------------------------------
+// Storage codecs.  C is the compute type.
+// ---------------------------------------------------------------------------
+struct StoreF64 {
+  using T = double;
+  using C = double;
+  static __device__ __forceinline__ C dec(T v, C) { return v; }
+  static __device__ __forceinline__ T enc(C v, C) { return v; }
+};
+struct StoreF32 {
+  using T = float;
+  using C = float;
+  static __device__ __forceinline__ C dec(T v, C) { return v; }
+  static __device__ __forceinline__ T enc(C v, C) { return v; }
+};
+// bfloat16 bits in a uint16_t, round-to-nearest-even; scaled by a power of two.
+struct StoreBF16 {
+  using T = uint16_t;
+  using C = float;
+  static __device__ __forceinline__ C dec(T v, C inv_scale) {
+    return __uint_as_float(uint32_t(v) << 16) * inv_scale;
+  }
+  static __device__ __forceinline__ T enc(C v, C scale) {
+    float s = v * scale;
+    if (s != s) return uint16_t(0x7FC0);
+    uint32_t u = __float_as_uint(s);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return uint16_t(u >> 16);
+  }
+};
+// IEEE binary16, hardware round-to-nearest-even; scaled by a power of two.
+struct StoreF16 {
+  using T = _Float16;
+  using C = float;
+  static __device__ __forceinline__ C dec(T v, C inv_scale) { return float(v) * inv_scale; }
+  static __device__ __forceinline__ T enc(C v, C scale) { return _Float16(v * scale); }
+};
+
+// ---------------------------------------------------------------------------
+// Per-lattice constants (derived once on the host from nu, gamma, omegas).
+// ---------------------------------------------------------------------------
+template <class C>
+struct Consts {
+  C rho0;
+  C ig;      // 1/gamma
+  C third;   // 3/gamma - 1/gamma^2 (Sec. 5) or 2 (eq. 4)
+  C A, B, Cg;            // A_gamma, B_gamma, C_gamma
+  C h3, h4, h5;          // 1/w - 1/2
+  C a3, a4;              // 2/(3 w)
+  C w3, w4, w5, w6, w7, w8;
+  C fx, fy;              // uniform body force
+  C u_lid, u_in_max;
+  C scale, inv_scale;    // storage scale (1 for F32/F64)
+  int gi;                // 1: Sec. 5 kernel; 0: eq. 4
+  int force;             // body force present
+  int stencil;           // 0 isotropic, 1 central
+};
+
+struct Geom {
+  int nx, ny;
+  int side[4];
+  long long plane;  // nx * ny
+};
+
+// ---------------------------------------------------------------------------
+// Equilibrium deviation f^eq - w rho0 at (rho0 + drho, u): the Sec. 3 raw
+// equilibria (orders <= 3), the central fourth-order target rho/9, mapped to
+// populations with the inverse of the raw-moment basis.
+// ---------------------------------------------------------------------------
+template <class C>
+__device__ __forceinline__ void equilibrium_dev(C drho, C ux, C uy, const Consts<C>& k, C f[9]) {
+  const C rho = k.rho0 + drho;
+  const C ig = k.ig;
+  const C ux2 = ux * ux, uy2 = uy * uy;
+  const C g1 = ig - C(1), g2 = ig - C(2);
+  // central targets about u
+  const C cxx = rho * (C(1) / C(3) + ux2 * g1);
+  const C cyy = rho * (C(1) / C(3) + uy2 * g1);
+  const C cxy = rho * ux * uy * g1;
+  const C cxxy = rho * ux2 * uy * g1 * g2;
+  const C cxyy = rho * ux * uy2 * g1 * g2;
+  // raw moments of the deviation (rest moments removed analytically)
+  const C m0 = drho;
+  const C mx = rho * ux, my = rho * uy;
+  const C mxx = drho * (C(1) / C(3)) + rho * ux2 * ig;
+  const C myy = drho * (C(1) / C(3)) + rho * uy2 * ig;
+  const C mxy = rho * ux * uy * ig;
+  const C mxxy = rho * uy * (C(1) / C(3)) + rho * ux2 * uy * ig * ig;
+  const C mxyy = rho * ux * (C(1) / C(3)) + rho * ux * uy2 * ig * ig;
+  const C mxxyy = drho * (C(1) / C(9)) + C(2) * ux * cxyy + C(2) * uy * cxxy + ux2 * cyy +
+                  uy2 * cxx + C(4) * ux * uy * cxy + rho * ux2 * uy2;
+  f[0] = m0 - mxx - myy + mxxyy;
+  f[1] = C(0.5) * (mx + mxx - mxyy - mxxyy);
+  f[2] = C(0.5) * (my + myy - mxxy - mxxyy);
+  f[3] = C(0.5) * (-mx + mxx + mxyy - mxxyy);
+  f[4] = C(0.5) * (-my + myy + mxxy - mxxyy);
+  f[5] = C(0.25) * (mxy + mxxy + mxyy + mxxyy);
+  f[6] = C(0.25) * (-mxy + mxxy - mxyy + mxxyy);
+  f[7] = C(0.25) * (mxy - mxxy - mxyy + mxxyy);
+  f[8] = C(0.25) * (-mxy - mxxy + mxyy + mxxyy);
+}
+
+// density deviation and velocity of a post-stream node (forcing shifts the
+// momentum by F/(2 gamma))
+template <class C>
+__device__ __forceinline__ void macro(const C d[9], const Consts<C>& k, C& drho, C& ux, C& uy) {
+  drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
+  C jx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
+  C jy = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
+  if (k.force) {
+    jx += C(0.5) * k.fx * k.ig;
+    jy += C(0.5) * k.fy * k.ig;
+  }
+  const C inv = C(1) / (k.rho0 + drho);
+  ux = jx * inv;
+  uy = jy * inv;
+}
+
+// ---------------------------------------------------------------------------
+// Collision of one node (eq. 2a with the cascaded kernel of Sec. 5, or eq. 4
+// when gi == 0).  d: post-stream deviations in, post-collision deviations out.
+// drx, dry: density gradient.  Returns whether the strain guard fired.
+// ---------------------------------------------------------------------------
+template <class C>
+__device__ __forceinline__ int collide(C d[9], C drx, C dry, const Consts<C>& k, C& drho_o,
+                                       C& ux_o, C& uy_o) {
+  const C s56 = d[5] + d[6], s78 = d[7] + d[8];
+  const C drho = ((d[0] + d[1]) + (d[2] + d[3])) + (d[4] + (s56 + s78));
+  C jx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
+  C jy = (d[2] - d[4]) + s56 - s78;
+  // raw moments of the deviation
+  C Kxx = (d[1] + d[3]) + (s56 + s78);
+  C Kyy = (d[2] + d[4]) + (s56 + s78);
+  C Kxy = (d[5] - d[6]) + (d[7] - d[8]);
+  C Kxxy = s56 - s78;
+  C Kxyy = (d[5] - d[6]) - (d[7] - d[8]);
+  C Kxxyy = s56 + s78;
+  if (k.force) {
+    jx += C(0.5) * k.fx * k.ig;
+    jy += C(0.5) * k.fy * k.ig;
+  }
+  const C rho = k.rho0 + drho;
+  const C inv_rho = C(1) / rho;
+  const C ux = jx * inv_rho, uy = jy * inv_rho;
+  const C ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
+  // source raw moments sigma' (Sec. 3); moments below are those of f = fbar + S/2
+  C s[9];
+  if (k.force) {
+    const C ig2 = k.ig * k.ig;
+    s[0] = C(0);
+    s[1] = k.fx * k.ig;
+    s[2] = k.fy * k.ig;
+    s[3] = C(2) * k.fx * ux * ig2;
+    s[4] = C(2) * k.fy * uy * ig2;
+    s[5] = (k.fx * uy + k.fy * ux) * ig2;
+    s[6] = k.fy * ux2 + C(2) * k.fx * uxy;
+    s[7] = k.fx * uy2 + C(2) * k.fy * uxy;
+    s[8] = C(2) * (k.fx * ux * uy2 + k.fy * uy * ux2);
+    Kxx += C(0.5) * s[3];
+    Kyy += C(0.5) * s[4];
+    Kxy += C(0.5) * s[5];
+    Kxxy += C(0.5) * s[6];
+    Kxyy += C(0.5) * s[7];
+    Kxxyy += C(0.5) * s[8];
+  }
+  // second-order non-equilibrium moments (rest parts cancel: 2 rho0/3 - 2 rho0/3)
+  const C m3 = (Kxx + Kyy) - C(2) / C(3) * drho - rho * (ux2 + uy2) * k.ig;
+  const C m4 = (Kxx - Kyy) - rho * (ux2 - uy2) * k.ig;
+
+  C D3 = C(0), D4 = C(0), D5 = C(0);
+  int guarded = 0;
+  if (k.gi) {
+    const C Aux2 = k.A * ux2, Auy2 = k.A * uy2, Bux2 = k.B * ux2, Buy2 = k.B * uy2;
+    // local strain rates from the 2x2 system of eqs. 51-53 (eq. 55, sign of
+    // the c~1 term as given by Cramer's rule)
+    const C er = k.Cg * (C(1) / C(3)) * (ux * drx + uy * dry);
+    const C ert = k.Cg * (C(1) / C(3)) * (ux * drx - uy * dry);
+    C c1 = rho * (k.a3 - C(0.5) * (Aux2 + Buy2));
+    C c2 = rho * (k.a3 - C(0.5) * (Auy2 + Bux2));
+    C ct1 = rho * (k.a4 - C(0.5) * (Aux2 - Buy2));
+    C ct2 = rho * (k.a4 - C(0.5) * (Auy2 - Bux2));
+    C D = -(c1 * ct2 + ct1 * c2);
+    const C D0 = C(-2) * k.a3 * k.a4 * rho * rho;
+    if (D * D0 <= C(0) || fabs(D) < C(0.25) * fabs(D0)) {
+      // singular-system guard: the gamma-free (A = B = 0) system
+      c1 = c2 = rho * k.a3;
+      ct1 = ct2 = rho * k.a4;
+      D = D0;
+      guarded = 1;
+    }
+    const C R3 = m3 - er, R4 = m4 - ert;
+    const C invD = C(1) / D;
+    const C dxux = (ct2 * R3 + c2 * R4) * invD;
+    const C dyuy = (ct1 * R3 - c1 * R4) * invD;
+    // extended-equilibrium corrections, eqs. 33 with 45-47
+    D3 = -k.h3 * rho * ((Aux2 + Buy2) * dxux + (Auy2 + Bux2) * dyuy) -
+         C(2) / C(3) * k.h3 * k.Cg * (ux * drx + uy * dry);
+    D4 = -k.h4 * rho * ((Aux2 - Buy2) * dxux + (Bux2 - Auy2) * dyuy) -
+         C(2) / C(3) * k.h4 * k.Cg * (ux * drx - uy * dry);
+    D5 = -k.h5 * rho * k.B * uxy * (dxux + dyuy) -
+         C(1) / C(3) * k.h5 * k.Cg * (uy * drx + ux * dry);
+  }
+  // cascaded moment changes (Sec. 5); K background parts written out:
+  // Kxx = rho0/3 + Kxx(dev), Kyy likewise, Kxxyy = rho0/9 + Kxxyy(dev)
+  const C r03 = k.rho0 * (C(1) / C(3));
+  const C g3 = k.w3 * (C(1) / C(12)) * (D3 - m3);
+  const C g4 = k.w4 * C(0.25) * (D4 - m4);
+  const C g5 = k.w5 * C(0.25) * (rho * uxy * k.ig - Kxy + D5);
+  const C g6 = k.w6 * C(0.25) * (k.third * rho * ux2 * uy + Kxxy - C(2) * ux * Kxy - uy * (r03 + Kxx)) -
+               C(0.5) * uy * (C(3) * g3 + g4) - C(2) * ux * g5;
+  const C g7 = k.w7 * C(0.25) * (k.third * rho * ux * uy2 + Kxyy - C(2) * uy * Kxy - ux * (r03 + Kyy)) -
+               C(0.5) * ux * (C(3) * g3 - g4) - C(2) * uy * g5;
+  const C g8 = k.w8 * C(0.25) *
+                   (drho * (C(1) / C(9)) + C(3) * rho * ux2 * uy2 -
+                    (Kxxyy - C(2) * ux * Kxyy - C(2) * uy * Kxxy + ux2 * (r03 + Kyy) +
+                     uy2 * (r03 + Kxx) + C(4) * uxy * Kxy)) -
+               C(2) * g3 - C(0.5) * uy2 * (C(3) * g3 + g4) - C(0.5) * ux2 * (C(3) * g3 - g4) -
+               C(4) * uxy * g5 - C(2) * uy * g6 - C(2) * ux * g7;
+  // back to populations: f~ = fbar + K g + S (columns of K written per velocity)
+  const C t2g3 = C(2) * g3;
+  d[0] += C(4) * (g8 - g3);
+  d[1] += (g4 - g3) + C(2) * (g7 - g8);
+  d[2] += -(g3 + g4) + C(2) * (g6 - g8);
+  d[3] += (g4 - g3) - C(2) * (g7 + g8);
+  d[4] += -(g3 + g4) - C(2) * (g6 + g8);
+  d[5] += t2g3 + g5 - g6 - g7 + g8;
+  d[6] += t2g3 - g5 - g6 + g7 + g8;
+  d[7] += t2g3 + g5 + g6 + g7 + g8;
+  d[8] += t2g3 - g5 + g6 - g7 + g8;
+  if (k.force) {
+    // S = inverse raw-moment map of sigma'
+    d[0] += s[0] - s[3] - s[4] + s[8];
+    d[1] += C(0.5) * (s[1] + s[3] - s[7] - s[8]);
+    d[2] += C(0.5) * (s[2] + s[4] - s[6] - s[8]);
+    d[3] += C(0.5) * (-s[1] + s[3] + s[7] - s[8]);
+    d[4] += C(0.5) * (-s[2] + s[4] + s[6] - s[8]);
+    d[5] += C(0.25) * (s[5] + s[6] + s[7] + s[8]);
+    d[6] += C(0.25) * (-s[5] + s[6] - s[7] + s[8]);
+    d[7] += C(0.25) * (s[5] - s[6] - s[7] + s[8]);
+    d[8] += C(0.25) * (-s[5] - s[6] + s[7] + s[8]);
+  }
+  drho_o = drho;
+  ux_o = ux;
+  uy_o = uy;
+  return guarded;
+}
+
+// ---------------------------------------------------------------------------
+// Pull with boundary links for fluid node (x, y) inside the lattice.
+// Returns the post-stream deviation of population a.  Sets *outlet when the
+// link crosses an OUTLET side (the caller fills it).
+// ---------------------------------------------------------------------------
+template <class S>
+__device__ __forceinline__ typename S::C pull_general(const typename S::T* __restrict__ fa,
+                                                      const uint8_t* __restrict__ solid,
+                                                      const Geom& g, const Consts<typename S::C>& k,
+                                                      int a, int x, int y, bool* outlet) {
+  using C = typename S::C;
+  int sx = x - ex_of(a), sy = y - ey_of(a);
+  int xs = -1, ys = -1;
+  if (sx < 0) {
+    if (g.side[kW] == kPeriodic) sx += g.nx; else xs = kW;
+  } else if (sx >= g.nx) {
+    if (g.side[kE] == kPeriodic) sx -= g.nx; else xs = kE;
+  }
+  if (sy < 0) {
+    if (g.side[kS] == kPeriodic) sy += g.ny; else ys = kS;
+  } else if (sy >= g.ny) {
+    if (g.side[kN] == kPeriodic) sy -= g.ny; else ys = kN;
+  }
+  const long long own = (long long)y * g.nx + x;
+  if (xs >= 0 || ys >= 0) {
+    const C bb = S::dec(fa[(long long)opp_of(a) * g.plane + own], k.inv_scale);
+    if (xs >= 0 && ys >= 0) return bb;  // corner link: stationary wall
+    const int sd = xs >= 0 ? xs : ys;
+    const int kind = g.side[sd];
+    if (kind == kOutlet) {
+      *outlet = true;
+      return C(0);
+    }
+    if (kind == kWall) return bb;
+    C uwx = C(0), uwy = C(0);
+    if (kind == kLid) {
+      if (sd == kS || sd == kN) uwx = k.u_lid; else uwy = k.u_lid;
+    } else {  // inlet (W side): parabolic profile at the node's y
+      const C H = C(g.ny), yy = C(y) + C(0.5);
+      uwx = C(4) * k.u_in_max * yy * (H - yy) / (H * H);
+    }
+    return bb + C(6) * w_of<C>(a) * k.rho0 * (C(ex_of(a)) * uwx + C(ey_of(a)) * uwy);
+  }
+  const long long src = (long long)sy * g.nx + sx;
+  if (solid && solid[src]) return S::dec(fa[(long long)opp_of(a) * g.plane + own], k.inv_scale);
+  return S::dec(fa[(long long)a * g.plane + src], k.inv_scale);
+}
+
+// All nine post-stream deviations of fluid node (x, y), general path.  When
+// some link crosses the outlet, fills it by non-equilibrium extrapolation
+// from node (nx-2, y) with the convective outlet velocity
+// u* = (u*_old + U u(nx-2)) / (1 + U) and density rho0; returns u* in us, vs.
+template <class S>
+__device__ __forceinline__ bool pull_node_general(const typename S::T* __restrict__ fa,
+                                                  const uint8_t* __restrict__ solid,
+                                                  const Geom& g, const Consts<typename S::C>& k,
+                                                  const typename S::C* __restrict__ hist_in, int x,
+                                                  int y, typename S::C d[9], typename S::C& us,
+                                                  typename S::C& vs) {
+  using C = typename S::C;
+  bool outl[9];
+  bool any = false;
+#pragma unroll
+  for (int a = 0; a < 9; ++a) {
+    outl[a] = false;
+    d[a] = pull_general<S>(fa, solid, g, k, a, x, y, &outl[a]);
+    any |= outl[a];
+  }
+  if (any) {
+    C d2[9];
+    bool dummy = false;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) d2[a] = pull_general<S>(fa, solid, g, k, a, g.nx - 2, y, &dummy);
+    C r2, u2, v2;
+    macro<C>(d2, k, r2, u2, v2);
+    const C U = k.u_in_max;
+    const C invU = C(1) / (C(1) + U);
+    us = (hist_in[y] + U * u2) * invU;
+    vs = (hist_in[g.ny + y] + U * v2) * invU;
+    C e2[9], eo[9];
+    equilibrium_dev<C>(r2, u2, v2, k, e2);
+    equilibrium_dev<C>(C(0), us, vs, k, eo);
+#pragma unroll
+    for (int a = 0; a < 9; ++a)
+      if (outl[a]) d[a] = eo[a] + (d2[a] - e2[a]);
+  }
+  return any;
+}
+
+}  // namespace lbmk

@@ -1,0 +1,278 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Each case prints its name, shape and seed before the GPU work starts.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import (SplitMix64, cavity_sides, channel_sides, diagonal_shear_wave,
+                       periodic_sides, poiseuille_sides, random_obstacles)
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1806_10251_amd import lbm as L
+    L.load()
+    return L
+
+
+def run_pair(L, nx, ny, sides, steps, solid=None, storage="f64", init=None, launch=None,
+             check_every=1, **params):
+    o = oracle.Oracle(nx, ny, sides, solid=solid, **params)
+    g = L.Lattice(nx, ny, sides, solid=solid, storage=storage, check_every=check_every, **params)
+    if launch:
+        g.set_launch(*launch)
+    if init is not None:
+        o.init_fields(*init)
+        g.init_fields(*init)
+    o.step(steps)
+    g.step(steps)
+    return o, g
+
+
+def test_c1_cavity_32_fp64_5000_steps(lbm):
+    """Config C1: 32x32 cavity, Re 100, gamma 0.5, U_lid 0.1, 5000 steps, FP64."""
+    _say("C1 cavity 32x32 f64 5000 steps")
+    U = 0.1
+    o, g = run_pair(lbm, 32, 32, cavity_sides(), 5000, nu=U * 32 / 100, gamma=0.5, u_lid=U)
+    ro, uxo, uyo = o.fields()
+    rg, uxg, uyg = g.fields()
+    err = max(np.abs(uxg - uxo).max(), np.abs(uyg - uyo).max()) / U
+    _say("C1 max|du|/U =", err)
+    assert err <= 1e-5
+    assert err <= 1e-11           # FP64 on both sides: rounding-order differences only
+    assert np.abs(rg - ro).max() < 1e-11
+    assert abs(g.residual - o.residual) <= 1e-6 * o.residual
+    assert abs(g.mass - o.mass) < 1e-9
+
+
+def test_c1_cavity_32_fp32_5000_steps(lbm):
+    _say("C1 cavity 32x32 f32 5000 steps")
+    U = 0.1
+    o, g = run_pair(lbm, 32, 32, cavity_sides(), 5000, storage="f32", nu=U * 32 / 100,
+                    gamma=0.5, u_lid=U)
+    _, uxo, uyo = o.fields()
+    _, uxg, uyg = g.fields()
+    err = max(np.abs(uxg - uxo).max(), np.abs(uyg - uyo).max()) / U
+    _say("C1 f32 max|du|/U =", err)
+    assert err <= 1e-5
+
+
+def _obstacle_mask(nx, ny, seed, kind="channel"):
+    return random_obstacles(SplitMix64(seed), nx, ny, kind)
+
+
+TINY = [
+    # name, nx, ny, sides, kwargs, steps
+    ("periodic-wave", 9, 7, periodic_sides(), dict(nu=0.03, gamma=0.4), 30),
+    ("cavity", 6, 5, cavity_sides(), dict(nu=0.02, gamma=0.5, u_lid=0.1), 40),
+    ("poiseuille-force", 5, 8, poiseuille_sides(), dict(nu=0.05, gamma=0.6, fx=1e-4, fy=-3e-5), 40),
+    ("channel", 16, 7, channel_sides(), dict(nu=0.05, gamma=0.5, u_in_max=0.05), 40),
+    ("uncorrected", 8, 8, cavity_sides(), dict(nu=0.02, gamma=0.3, u_lid=0.05, gi_correct=0), 40),
+    ("central-fd", 8, 8, cavity_sides(), dict(nu=0.02, gamma=0.3, u_lid=0.05, drho_stencil=1), 40),
+    ("lid-on-west", 7, 6, (2, 1, 1, 1), dict(nu=0.02, gamma=0.5, u_lid=0.08), 30),
+    ("periodic-x-walls-y", 6, 6, poiseuille_sides(), dict(nu=0.04, gamma=1.0, u_lid=0.0), 30),
+]
+
+
+@pytest.mark.parametrize("case", TINY, ids=[c[0] for c in TINY])
+def test_tiny_grids_every_boundary_fp64(lbm, case):
+    name, nx, ny, sides, kw, steps = case
+    _say("tiny", name, nx, ny)
+    rng = SplitMix64(99)
+    init = None
+    if sides == periodic_sides() or name == "poiseuille-force":
+        rho = 1.0 + 0.01 * rng.uniform_array(nx * ny, -1, 1).reshape(ny, nx)
+        ux = 0.02 * rng.uniform_array(nx * ny, -1, 1).reshape(ny, nx)
+        uy = 0.02 * rng.uniform_array(nx * ny, -1, 1).reshape(ny, nx)
+        init = (rho, ux, uy)
+    o, g = run_pair(lbm, nx, ny, sides, steps, init=init, **kw)
+    fo, fg = o.get_f(), g.populations()
+    np.testing.assert_allclose(fg, fo, rtol=0, atol=1e-13)
+
+
+def test_single_solid_cell_and_obstacles_fp64(lbm):
+    nx, ny = 20, 11
+    m = np.zeros((ny, nx), np.uint8)
+    m[5, 8] = 1          # single solid cell
+    m[2:4, 12:15] = 1    # a block
+    _say("solids", nx, ny)
+    o, g = run_pair(lbm, nx, ny, channel_sides(), 60, solid=m, nu=0.04, gamma=0.5,
+                    u_in_max=0.05)
+    fo, fg = o.get_f(), g.populations()
+    fl = m == 0
+    np.testing.assert_allclose(fg[:, fl], fo[:, fl], rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_ragged_multi_tile_every_launch_shape(lbm, storage, tol):
+    """150 x 77 with obstacles: several tiles in x and y and ragged tails."""
+    nx, ny = 150, 77
+    m = _obstacle_mask(nx, ny, 5, "cavity")
+    U = 0.08
+    o = oracle.Oracle(nx, ny, cavity_sides(), solid=m, nu=0.05, gamma=0.5, u_lid=U)
+    o.step(120)
+    _, uxo, uyo = o.fields()
+    for shape in lbm.launch_shapes():
+        _say("ragged", storage, shape)
+        g = lbm.Lattice(nx, ny, cavity_sides(), solid=m, storage=storage, nu=0.05, gamma=0.5,
+                        u_lid=U)
+        g.set_launch(*shape)
+        g.step(120)
+        _, uxg, uyg = g.fields()
+        err = max(np.abs(uxg - uxo).max(), np.abs(uyg - uyo).max()) / U
+        assert err < tol, (shape, err)
+        g.close()
+
+
+def test_channel_with_obstacle_multi_tile_fp64(lbm):
+    nx, ny = 200, 40
+    m = np.zeros((ny, nx), np.uint8)
+    m[15:25, 60:70] = 1
+    _say("channel obstacle", nx, ny)
+    o, g = run_pair(lbm, nx, ny, channel_sides(), 300, solid=m, nu=0.05, gamma=0.3,
+                    u_in_max=0.04)
+    _, uxo, uyo = o.fields()
+    _, uxg, uyg = g.fields()
+    assert max(np.abs(uxg - uxo).max(), np.abs(uyg - uyo).max()) / 0.04 < 1e-12
+
+
+def test_graph_replay_matches_single_launches(lbm):
+    """check_every = 8 runs through captured graphs; check_every = 1 through
+    single launches; identical FP64 populations."""
+    _say("graph vs launches")
+    kw = dict(nu=0.02, gamma=0.5, u_lid=0.1)
+    a = lbm.Lattice(40, 30, cavity_sides(), storage="f64", check_every=1, **kw)
+    b = lbm.Lattice(40, 30, cavity_sides(), storage="f64", check_every=8, **kw)
+    for _ in range(5):
+        a.step(37)
+        b.step(37)
+        b.step(11)
+        a.step(11)
+    np.testing.assert_array_equal(a.populations(), b.populations())
+    assert abs(a.residual - b.residual) <= 1e-12 * a.residual or b.steps % 8 != 0
+
+
+def test_residual_and_mass_match_oracle(lbm):
+    _say("residual/mass")
+    o, g = run_pair(lbm, 24, 24, cavity_sides(), 300, nu=0.024, gamma=0.5, u_lid=0.1)
+    assert abs(g.residual - o.residual) / o.residual < 1e-8
+    assert abs(g.mass - o.mass) < 1e-10
+    assert abs(g.mass - 24 * 24) < 1e-9
+    assert g.guard_count == o.guard_count
+
+
+def test_checkpoint_resume_is_bit_exact(lbm, tmp_path):
+    _say("checkpoint")
+    kw = dict(nu=0.02, gamma=0.5, u_lid=0.1, storage="f32")
+    a = lbm.Lattice(50, 40, cavity_sides(), **kw)
+    a.step(100)
+    a.save(tmp_path / "ck.bin")
+    a.step(100)
+    b = lbm.Lattice(50, 40, cavity_sides(), **kw)
+    b.load_checkpoint(tmp_path / "ck.bin")
+    assert b.steps == 100
+    b.step(100)
+    np.testing.assert_array_equal(a.populations(), b.populations())
+
+
+def test_device_init_matches_host_init(lbm):
+    import torch
+    _say("device init")
+    n = 33
+    rho, ux, uy = diagonal_shear_wave(n, 1e-3, 2, 0.05)
+    a = lbm.Lattice(n, n, periodic_sides(), storage="f32", nu=0.02, gamma=0.5)
+    b = lbm.Lattice(n, n, periodic_sides(), storage="f32", nu=0.02, gamma=0.5)
+    a.init_fields(rho, ux, uy)
+    t = [torch.tensor(v, dtype=torch.float32, device="cuda") for v in (rho, ux, uy)]
+    torch.cuda.synchronize()
+    b.init_fields_device(*t)
+    a.step(10)
+    b.step(10)
+    np.testing.assert_allclose(a.populations(), b.populations(), atol=1e-7)
+    out = [torch.zeros(n, n, device="cuda") for _ in range(3)]
+    a.fields_device(*out)
+    torch.cuda.synchronize()
+    _, uxa, _ = a.fields()
+    np.testing.assert_allclose(out[1].cpu().numpy(), uxa, atol=1e-7)
+
+
+@pytest.mark.parametrize("storage,tol", [("bf16", 3e-2), ("f16", 3e-3)])
+def test_reduced_storage_error_vs_oracle(lbm, storage, tol):
+    """BF16/FP16 deviation storage with FP32 compute: error against the FP64
+    oracle is bounded (reported, not round-off)."""
+    _say("storage", storage)
+    U = 0.1
+    o, g = run_pair(lbm, 48, 48, cavity_sides(), 2000, storage=storage, nu=U * 48 / 100,
+                    gamma=0.5, u_lid=U)
+    _, uxo, uyo = o.fields()
+    _, uxg, uyg = g.fields()
+    err = max(np.abs(uxg - uxo).max(), np.abs(uyg - uyo).max()) / U
+    _say(storage, "max|du|/U", err)
+    assert err < tol
+
+
+def test_full_size_cavity_1024_fp32_against_oracle(lbm):
+    """Config C2 size (1024^2, Re 1000) in the default launch shape: all nodes
+    after 20 steps against the oracle run at the same size."""
+    n, U = 1024, 0.1
+    _say("C2 1024^2 f32 20 steps")
+    o, g = run_pair(lbm, n, n, cavity_sides(), 20, storage="f32", nu=U * n / 1000, gamma=0.5,
+                    u_lid=U)
+    _, uxo, uyo = o.fields()
+    _, uxg, uyg = g.fields()
+    err = max(np.abs(uxg - uxo).max(), np.abs(uyg - uyo).max()) / U
+    _say("C2 max|du|/U", err)
+    assert err <= 1e-5
+
+
+def test_unstable_run_reports_error(lbm):
+    _say("unstable")
+    g = lbm.Lattice(32, 32, cavity_sides(), storage="f32", nu=0.0032, gamma=0.05, u_lid=0.1)
+    with pytest.raises(lbm.UnstableError):
+        for _ in range(60):
+            g.step(100)
+            g.residual
+
+
+def test_gi_shear_wave_gpu(lbm):
+    """GI check on the GPU: diagonal shear-wave decay independent of Ux."""
+    n, m, gamma = 128, 2, 0.5
+    k = 2 * math.pi * m / n
+    exact = 0.05 * 2 * k * k
+    x = np.arange(n) + 0.5
+    X, Y = np.meshgrid(x, x)
+    ph = np.exp(-1j * k * (X + Y))
+    rates = {}
+    for gi in (1, 0):
+        for ux0 in (0.0, 0.1):
+            _say("shear wave", gi, ux0)
+            g = lbm.Lattice(n, n, periodic_sides(), storage="f32", nu=0.05 * gamma,
+                            gamma=gamma, gi_correct=gi)
+            g.init_fields(*diagonal_shear_wave(n, 1e-3, m, ux0))
+            ts, la = [], []
+            for _ in range(20):
+                g.step(50)
+                _, ux, uy = g.fields()
+                ts.append(g.steps)
+                la.append(math.log(abs((((ux - uy) / math.sqrt(2)) * ph).mean())))
+            ts, la = np.array(ts), np.array(la)
+            rates[(gi, ux0)] = -np.polyfit(ts[4:], la[4:], 1)[0]
+    assert abs(rates[(1, 0.0)] - exact) / exact < 5e-3
+    assert abs(rates[(1, 0.1)] - rates[(1, 0.0)]) / exact < 3e-3
+    assert abs(rates[(0, 0.1)] - rates[(0, 0.0)]) / exact > 0.03
