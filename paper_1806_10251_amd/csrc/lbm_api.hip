@@ -38,8 +38,8 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict_
   if (t < 4) out[t] = s[t][0];
 }
 
-// Equilibrium initialisation from optional device fields (float); also
-// writes the velocity buffer and the outlet history.
+// Equilibrium initialisation from optional device fields; also writes the
+// velocity buffer and the outlet history.  Interior nodes of both lattices.
 template <class S, class FT>
 __global__ __launch_bounds__(256) void init_kernel(typename S::T* __restrict__ fa,
                                                    typename S::T* __restrict__ fb, Geom g,
@@ -52,8 +52,9 @@ __global__ __launch_bounds__(256) void init_kernel(typename S::T* __restrict__ f
                                                    typename S::C* __restrict__ hist0,
                                                    typename S::C* __restrict__ hist1) {
   using C = typename S::C;
+  const long long np = (long long)g.nx * g.ny;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.plane) return;
+  if (i >= np) return;
   const bool sol = solid && solid[i];
   C drho = C(0), vx = C(0), vy = C(0);
   if (!sol) {
@@ -63,21 +64,45 @@ __global__ __launch_bounds__(256) void init_kernel(typename S::T* __restrict__ f
   }
   C f[9];
   equilibrium_dev<C>(drho, vx, vy, k, f);
+  const int x = int(i % g.nx), y = int(i / g.nx);
+  const long long li = gidx(g, x, y);
 #pragma unroll
   for (int a = 0; a < 9; ++a) {
     const typename S::T v = S::enc(f[a], k.scale);
-    fa[a * g.plane + i] = v;
-    fb[a * g.plane + i] = v;
+    fa[a * g.plane + li] = v;
+    fb[a * g.plane + li] = v;
   }
   ubuf[i] = vx;
-  ubuf[g.plane + i] = vy;
-  const int x = int(i % g.nx), y = int(i / g.nx);
+  ubuf[np + i] = vy;
   if (x == g.nx - 1) {
     hist0[y] = vx;
     hist0[g.ny + y] = vy;
     hist1[y] = vx;
     hist1[g.ny + y] = vy;
   }
+}
+
+// Boundary slots of a lattice from its own fluid-node values (after an
+// initialisation or a checkpoint load).
+template <class S>
+__global__ __launch_bounds__(256) void ghost_fill_kernel(typename S::T* __restrict__ fa, Geom g,
+                                                         Consts<typename S::C> k,
+                                                         const uint8_t* __restrict__ solid) {
+  using C = typename S::C;
+  const long long np = (long long)g.nx * g.ny;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  if (solid && solid[i]) return;
+  const int x = int(i % g.nx), y = int(i / g.nx);
+  C d[9];
+  const long long li = gidx(g, x, y);
+#pragma unroll
+  for (int a = 0; a < 9; ++a) d[a] = S::dec(fa[a * g.plane + li], k.inv_scale);
+  auto nonfluid = [&](int a) {
+    int gx, gy;
+    return !region_node(g, solid, x - ex_of(a), y - ey_of(a), gx, gy);
+  };
+  ghost_writes<S>(fa, g, k, x, y, d, nonfluid);
 }
 
 // Decode populations (full f) or macroscopic fields of the current lattice.
@@ -93,15 +118,17 @@ __global__ __launch_bounds__(256) void export_kernel(const typename S::T* __rest
                                                      double* __restrict__ ux_d,
                                                      double* __restrict__ uy_d) {
   using C = typename S::C;
+  const long long np = (long long)g.nx * g.ny;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.plane) return;
+  if (i >= np) return;
+  const long long li = gidx(g, int(i % g.nx), int(i / g.nx));
   C d[9];
 #pragma unroll
-  for (int a = 0; a < 9; ++a) d[a] = S::dec(fa[a * g.plane + i], k.inv_scale);
+  for (int a = 0; a < 9; ++a) d[a] = S::dec(fa[a * g.plane + li], k.inv_scale);
   if (pops) {
 #pragma unroll
     for (int a = 0; a < 9; ++a)
-      pops[a * g.plane + i] = double(d[a]) + double(w_of<C>(a)) * double(k.rho0);
+      pops[a * np + i] = double(d[a]) + double(w_of<C>(a)) * double(k.rho0);
   }
   const bool sol = solid && solid[i];
   // post-collision moments: rho is unchanged by collision; the momentum has
@@ -143,7 +170,7 @@ int fail(int code, const std::string& msg) {
 struct Shape {
   int by, rows;
 };
-constexpr Shape kShapes[] = {{4, 4}, {8, 2}, {8, 4}, {16, 1}, {16, 2}, {4, 2}};
+constexpr Shape kShapes[] = {{16, 1}, {8, 1}, {4, 2}, {8, 2}, {16, 2}, {4, 4}, {8, 4}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
 size_t storage_bytes(int storage) {
@@ -167,7 +194,7 @@ struct lbm_ctx {
   void* lat[2] = {nullptr, nullptr};
   uint8_t* d_solid = nullptr;  // nullptr when no solid node
   std::vector<uint8_t> h_solid;
-  uint8_t* d_tile_fast = nullptr;
+
   void* hist[2] = {nullptr, nullptr};
   void* ubuf = nullptr;
   double* partials = nullptr;
@@ -175,7 +202,7 @@ struct lbm_ctx {
   int cur = 0;
   int64_t t = 0;
   bool checked = false;
-  int by = 4, rows = 4;
+  int by = 16, rows = 1;
   int tiles_x = 0, tiles_y = 0, ntiles = 0, out_rows = 0;
   size_t partial_cap = 0;
   Consts<double> kd{};
@@ -229,14 +256,21 @@ Consts<C> make_consts(const lbm_params& p, double scale) {
   return k;
 }
 
-Geom make_geom(const lbm_ctx* c) {
+// Framed, line-aligned layout: column 0 of every row starts a 128-byte line;
+// one ghost column/row on each side.
+Geom make_geom_for(int nx, int ny, const int32_t side[4], size_t esize) {
   Geom g{};
-  g.nx = c->grid.nx;
-  g.ny = c->grid.ny;
-  for (int s = 0; s < 4; ++s) g.side[s] = c->grid.side[s];
-  g.plane = (long long)g.nx * g.ny;
+  g.nx = nx;
+  g.ny = ny;
+  for (int s = 0; s < 4; ++s) g.side[s] = side[s];
+  const int line = int(128 / esize);  // elements per 128-byte line
+  g.padx = line;
+  g.pitch = ((nx + 2 * line) + line - 1) / line * line;
+  g.plane = (long long)g.pitch * (ny + 2);
   return g;
 }
+
+Geom make_geom(const lbm_ctx* c) { return make_geom_for(c->grid.nx, c->grid.ny, c->grid.side, c->esize); }
 
 int validate(const lbm_grid* grid, const uint8_t* solid, const lbm_params* p) {
   if (!grid || !p) return fail(LBM_EINVAL, "null grid or params");
@@ -269,41 +303,12 @@ int validate(const lbm_grid* grid, const uint8_t* solid, const lbm_params* p) {
   return LBM_OK;
 }
 
-// A tile is "fast" when its region grown by one node (the pull sources) lies
-// inside the lattice and holds no solid node.
-void compute_tile_flags(const lbm_ctx* c, std::vector<uint8_t>& flags) {
-  const int nx = c->grid.nx, ny = c->grid.ny;
-  flags.assign(c->ntiles, 0);
-  const int rr = c->by * c->rows;
-  for (int t = 0; t < c->ntiles; ++t) {
-    const int tx = t % c->tiles_x, ty = t / c->tiles_x;
-    const int x0 = tx * kOutX - 2, x1 = tx * kOutX - 1 + kLanes;  // inclusive
-    const int y0 = ty * c->out_rows - 2, y1 = ty * c->out_rows - 1 + rr;
-    if (x0 < 0 || y0 < 0 || x1 >= nx || y1 >= ny) continue;
-    bool ok = true;
-    if (!c->h_solid.empty())
-      for (int y = y0; y <= y1 && ok; ++y)
-        for (int x = x0; x <= x1; ++x)
-          if (c->h_solid[(size_t)y * nx + x]) {
-            ok = false;
-            break;
-          }
-    flags[t] = ok ? 1 : 0;
-  }
-}
-
 int configure_tiles(lbm_ctx* c) {
   const int rr = c->by * c->rows;
   c->out_rows = rr - 2;
-  c->tiles_x = (c->grid.nx + kOutX - 1) / kOutX;
+  c->tiles_x = (c->grid.nx + kLanes - 1) / kLanes;
   c->tiles_y = (c->grid.ny + c->out_rows - 1) / c->out_rows;
   c->ntiles = c->tiles_x * c->tiles_y;
-  std::vector<uint8_t> flags;
-  compute_tile_flags(c, flags);
-  if (c->d_tile_fast) HIPCHECK(hipFree(c->d_tile_fast));
-  c->d_tile_fast = nullptr;
-  HIPCHECK(hipMalloc(&c->d_tile_fast, c->ntiles));
-  HIPCHECK(hipMemcpy(c->d_tile_fast, flags.data(), c->ntiles, hipMemcpyHostToDevice));
   if ((size_t)c->ntiles > c->partial_cap) {
     if (c->partials) HIPCHECK(hipFree(c->partials));
     c->partials = nullptr;
@@ -331,7 +336,6 @@ void enqueue_step(lbm_ctx* c, hipStream_t st) {
   a.ntiles = c->ntiles;
   a.out_rows = c->out_rows;
   a.solid = c->d_solid;
-  a.tile_fast = c->d_tile_fast;
   a.hist_in = c->hist[c->cur];
   a.hist_out = c->hist[c->cur ^ 1];
   a.ubuf = c->ubuf;
@@ -339,18 +343,10 @@ void enqueue_step(lbm_ctx* c, hipStream_t st) {
   const void* src = c->lat[c->cur];
   void* dst = c->lat[c->cur ^ 1];
   switch (c->p.storage) {
-    case LBM_STORE_F64:
-      launch_step_f64(c->by, c->rows, flavor, src, dst, a, c->kd, c->ntiles, st);
-      break;
-    case LBM_STORE_F32:
-      launch_step_f32(c->by, c->rows, flavor, src, dst, a, c->kf, c->ntiles, st);
-      break;
-    case LBM_STORE_BF16:
-      launch_step_bf16(c->by, c->rows, flavor, src, dst, a, c->kf, c->ntiles, st);
-      break;
-    default:
-      launch_step_f16(c->by, c->rows, flavor, src, dst, a, c->kf, c->ntiles, st);
-      break;
+    case LBM_STORE_F64: launch_step_f64(c->by, c->rows, flavor, src, dst, a, c->kd, st); break;
+    case LBM_STORE_F32: launch_step_f32(c->by, c->rows, flavor, src, dst, a, c->kf, st); break;
+    case LBM_STORE_BF16: launch_step_bf16(c->by, c->rows, flavor, src, dst, a, c->kf, st); break;
+    default: launch_step_f16(c->by, c->rows, flavor, src, dst, a, c->kf, st); break;
   }
   if (flavor == kCheck) {
     hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, st, c->partials, c->ntiles,
@@ -366,10 +362,22 @@ void launch_init(lbm_ctx* c, const FT* rho, const FT* ux, const FT* uy) {
   using C = typename S::C;
   using T = typename S::T;
   Geom g = make_geom(c);
-  const int blocks = int((g.plane + 255) / 256);
+  const int blocks = int(((long long)g.nx * g.ny + 255) / 256);
   hipLaunchKernelGGL((init_kernel<S, FT>), dim3(blocks), dim3(256), 0, c->stream, (T*)c->lat[0],
                      (T*)c->lat[1], g, consts_for<C>(c), c->d_solid, rho, ux, uy, (C*)c->ubuf,
                      (C*)c->hist[0], (C*)c->hist[1]);
+  hipLaunchKernelGGL((ghost_fill_kernel<S>), dim3(blocks), dim3(256), 0, c->stream, (T*)c->lat[0],
+                     g, consts_for<C>(c), c->d_solid);
+}
+
+template <class S>
+void launch_ghost_fill(lbm_ctx* c, int which) {
+  using C = typename S::C;
+  using T = typename S::T;
+  Geom g = make_geom(c);
+  const int blocks = int(((long long)g.nx * g.ny + 255) / 256);
+  hipLaunchKernelGGL((ghost_fill_kernel<S>), dim3(blocks), dim3(256), 0, c->stream,
+                     (T*)c->lat[which], g, consts_for<C>(c), c->d_solid);
 }
 
 template <class FT>
@@ -395,7 +403,7 @@ int init_common(lbm_ctx* c, const FT* rho, const FT* ux, const FT* uy) {
 int export_common(lbm_ctx* c, double* pops, float* ro, float* uxo, float* uyo, double* rd,
                   double* uxd, double* uyd) {
   Geom g = make_geom(c);
-  const int blocks = int((g.plane + 255) / 256);
+  const int blocks = int(((long long)g.nx * g.ny + 255) / 256);
   const void* src = c->lat[c->cur];
   switch (c->p.storage) {
     case LBM_STORE_F64:
@@ -431,7 +439,6 @@ void free_ctx(lbm_ctx* c) {
     if (c->hist[i]) hipFree(c->hist[i]);
   }
   if (c->d_solid) hipFree(c->d_solid);
-  if (c->d_tile_fast) hipFree(c->d_tile_fast);
   if (c->ubuf) hipFree(c->ubuf);
   if (c->partials) hipFree(c->partials);
   if (c->result) hipFree(c->result);
@@ -484,10 +491,8 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid_mask, const lbm_params
   c->kf = make_consts<float>(c->p, scale);
   c->esize = storage_bytes(c->p.storage);
   c->csize = c->p.storage == LBM_STORE_F64 ? 8 : 4;
-  if (c->p.storage == LBM_STORE_F64) {
-    c->by = 8;
-    c->rows = 2;
-  }
+  c->by = 16;
+  c->rows = 1;
   auto dev = [&](hipError_t e, const char* what) {
     if (e != hipSuccess) {
       g_err = std::string(what) + ": " + hipGetErrorString(e);
@@ -499,8 +504,10 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid_mask, const lbm_params
   bool ok = dev(hipGetDevice(&c->device), "hipGetDevice") &&
             dev(hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking), "hipStreamCreate");
   c->stream = c->own_stream;
+  const Geom g0 = make_geom(c);
   for (int i = 0; ok && i < 2; ++i) {
-    ok = dev(hipMalloc(&c->lat[i], 9 * n * c->esize), "hipMalloc lattice") &&
+    ok = dev(hipMalloc(&c->lat[i], 9 * (size_t)g0.plane * c->esize), "hipMalloc lattice") &&
+         dev(hipMemset(c->lat[i], 0, 9 * (size_t)g0.plane * c->esize), "hipMemset lattice") &&
          dev(hipMalloc(&c->hist[i], 2 * (size_t)grid->ny * c->csize), "hipMalloc history");
   }
   ok = ok && dev(hipMalloc(&c->ubuf, 2 * n * c->csize), "hipMalloc velocity") &&
@@ -731,7 +738,8 @@ int lbm_save(lbm_ctx* c, const char* path) {
   if (!c || !path) return fail(LBM_EINVAL, "null argument");
   HIPCHECK(hipStreamSynchronize(c->stream));
   const size_t n = (size_t)c->grid.nx * c->grid.ny;
-  std::vector<char> lat(9 * n * c->esize), hist(2 * (size_t)c->grid.ny * c->csize);
+  const Geom g = make_geom(c);
+  std::vector<char> lat(9 * (size_t)g.plane * c->esize), hist(2 * (size_t)c->grid.ny * c->csize);
   HIPCHECK(hipMemcpy(lat.data(), c->lat[c->cur], lat.size(), hipMemcpyDeviceToHost));
   HIPCHECK(hipMemcpy(hist.data(), c->hist[c->cur], hist.size(), hipMemcpyDeviceToHost));
   std::vector<char> ub(2 * n * c->csize);
@@ -757,7 +765,8 @@ int lbm_load(lbm_ctx* c, const char* path) {
   int32_t hdr[8];
   int64_t t;
   const size_t n = (size_t)c->grid.nx * c->grid.ny;
-  std::vector<char> lat(9 * n * c->esize), hist(2 * (size_t)c->grid.ny * c->csize),
+  const Geom g = make_geom(c);
+  std::vector<char> lat(9 * (size_t)g.plane * c->esize), hist(2 * (size_t)c->grid.ny * c->csize),
       ub(2 * n * c->csize);
   bool ok = std::fread(mg, 1, 8, fp) == 8 && std::memcmp(mg, kMagic, 8) == 0 &&
             std::fread(hdr, sizeof hdr, 1, fp) == 1 && hdr[0] == c->grid.nx &&

@@ -1,7 +1,7 @@
 // Device-side building blocks of the fused D2Q9 step for gfx950:
 // storage codecs, the equilibrium, the GI-corrected preconditioned cascaded
 // collision and the pull with boundary links.  Shared by the single-lattice
-// kernel (lbm_step.hip) and the persistent batch kernel (lbm_batch.hip).
+// kernels (lbm_kernels.h) and the persistent batch kernel (lbm_batch.hip).
 //
 // Populations are held as deviations d_a = f_a - w_a rho0 throughout, so the
 // large rest part never enters a rounding step; every moment below is the
@@ -89,11 +89,22 @@ struct Consts {
   int stencil;           // 0 isotropic, 1 central
 };
 
+// Lattice geometry and storage layout.  Each population plane holds the
+// lattice inside a one-node ghost frame (x = -1 .. nx, y = -1 .. ny); rows are
+// padded so that column 0 of every row starts a 128-byte line.  Ghost and
+// solid slots hold the values that boundary links pull (written by the fluid
+// node that owns them; see ghost_writes), so the pull itself is uniform.
 struct Geom {
   int nx, ny;
   int side[4];
-  long long plane;  // nx * ny
+  int pitch;        // stored elements per row
+  int padx;         // offset of column 0 within a stored row
+  long long plane;  // pitch * (ny + 2)
 };
+
+__host__ __device__ __forceinline__ long long gidx(const Geom& g, int x, int y) {
+  return (long long)(y + 1) * g.pitch + g.padx + x;
+}
 
 // ---------------------------------------------------------------------------
 // Equilibrium deviation f^eq - w rho0 at (rho0 + drho, u): the Sec. 3 raw
@@ -279,92 +290,142 @@ __device__ __forceinline__ int collide(C d[9], C drx, C dry, const Consts<C>& k,
 }
 
 // ---------------------------------------------------------------------------
-// Pull with boundary links for fluid node (x, y) inside the lattice.
-// Returns the post-stream deviation of population a.  Sets *outlet when the
-// link crosses an OUTLET side (the caller fills it).
+// Streaming (eq. 2b) as a pull through the ghost frame: nine independent loads.
 // ---------------------------------------------------------------------------
 template <class S>
-__device__ __forceinline__ typename S::C pull_general(const typename S::T* __restrict__ fa,
-                                                      const uint8_t* __restrict__ solid,
-                                                      const Geom& g, const Consts<typename S::C>& k,
-                                                      int a, int x, int y, bool* outlet) {
-  using C = typename S::C;
-  int sx = x - ex_of(a), sy = y - ey_of(a);
-  int xs = -1, ys = -1;
-  if (sx < 0) {
-    if (g.side[kW] == kPeriodic) sx += g.nx; else xs = kW;
-  } else if (sx >= g.nx) {
-    if (g.side[kE] == kPeriodic) sx -= g.nx; else xs = kE;
-  }
-  if (sy < 0) {
-    if (g.side[kS] == kPeriodic) sy += g.ny; else ys = kS;
-  } else if (sy >= g.ny) {
-    if (g.side[kN] == kPeriodic) sy -= g.ny; else ys = kN;
-  }
-  const long long own = (long long)y * g.nx + x;
-  if (xs >= 0 || ys >= 0) {
-    const C bb = S::dec(fa[(long long)opp_of(a) * g.plane + own], k.inv_scale);
-    if (xs >= 0 && ys >= 0) return bb;  // corner link: stationary wall
-    const int sd = xs >= 0 ? xs : ys;
-    const int kind = g.side[sd];
-    if (kind == kOutlet) {
-      *outlet = true;
-      return C(0);
-    }
-    if (kind == kWall) return bb;
-    C uwx = C(0), uwy = C(0);
-    if (kind == kLid) {
-      if (sd == kS || sd == kN) uwx = k.u_lid; else uwy = k.u_lid;
-    } else {  // inlet (W side): parabolic profile at the node's y
-      const C H = C(g.ny), yy = C(y) + C(0.5);
-      uwx = C(4) * k.u_in_max * yy * (H - yy) / (H * H);
-    }
-    return bb + C(6) * w_of<C>(a) * k.rho0 * (C(ex_of(a)) * uwx + C(ey_of(a)) * uwy);
-  }
-  const long long src = (long long)sy * g.nx + sx;
-  if (solid && solid[src]) return S::dec(fa[(long long)opp_of(a) * g.plane + own], k.inv_scale);
-  return S::dec(fa[(long long)a * g.plane + src], k.inv_scale);
+__device__ __forceinline__ void pull9(const typename S::T* __restrict__ fa, const Geom& g,
+                                      const Consts<typename S::C>& k, int x, int y,
+                                      typename S::C d[9]) {
+  const long long own = gidx(g, x, y);
+#pragma unroll
+  for (int a = 0; a < 9; ++a)
+    d[a] = S::dec(fa[(long long)a * g.plane + own - ex_of(a) - (long long)ey_of(a) * g.pitch],
+                  k.inv_scale);
 }
 
-// All nine post-stream deviations of fluid node (x, y), general path.  When
-// some link crosses the outlet, fills it by non-equilibrium extrapolation
-// from node (nx-2, y) with the convective outlet velocity
-// u* = (u*_old + U u(nx-2)) / (1 + U) and density rho0; returns u* in us, vs.
+// Links of node (nx-1, y) that cross an OUTLET side (e_x = -1, source not a
+// corner), as a bit mask over the velocity index.
+__device__ __forceinline__ unsigned outlet_mask(const Geom& g, int y) {
+  unsigned m = 1u << 3;
+  const bool py = g.side[kS] == kPeriodic;
+  if (y - 1 >= 0 || py) m |= 1u << 6;       // e = (-1, 1): source (nx, y-1)
+  if (y + 1 < g.ny || py) m |= 1u << 7;     // e = (-1,-1): source (nx, y+1)
+  return m;
+}
+
+// Outlet links of node (nx-1, y): non-equilibrium extrapolation from node
+// (nx-2, y) at the same time level, with the convective outlet velocity
+// u* = (u*_old + U u(nx-2)) / (1 + U) and density rho0.  Returns u*.
 template <class S>
-__device__ __forceinline__ bool pull_node_general(const typename S::T* __restrict__ fa,
-                                                  const uint8_t* __restrict__ solid,
-                                                  const Geom& g, const Consts<typename S::C>& k,
-                                                  const typename S::C* __restrict__ hist_in, int x,
-                                                  int y, typename S::C d[9], typename S::C& us,
-                                                  typename S::C& vs) {
+__device__ __forceinline__ void outlet_links(const typename S::T* __restrict__ fa, const Geom& g,
+                                             const Consts<typename S::C>& k,
+                                             const typename S::C* __restrict__ hist_in, int y,
+                                             typename S::C d[9], typename S::C& us,
+                                             typename S::C& vs) {
   using C = typename S::C;
-  bool outl[9];
-  bool any = false;
+  C d2[9];
+  pull9<S>(fa, g, k, g.nx - 2, y, d2);
+  C r2, u2, v2;
+  macro<C>(d2, k, r2, u2, v2);
+  const C U = k.u_in_max;
+  const C invU = C(1) / (C(1) + U);
+  us = (hist_in[y] + U * u2) * invU;
+  vs = (hist_in[g.ny + y] + U * v2) * invU;
+  C e2[9], eo[9];
+  equilibrium_dev<C>(r2, u2, v2, k, e2);
+  equilibrium_dev<C>(C(0), us, vs, k, eo);
+  const unsigned m = outlet_mask(g, y);
 #pragma unroll
-  for (int a = 0; a < 9; ++a) {
-    outl[a] = false;
-    d[a] = pull_general<S>(fa, solid, g, k, a, x, y, &outl[a]);
-    any |= outl[a];
+  for (int a = 0; a < 9; ++a)
+    if (m & (1u << a)) d[a] = eo[a] + (d2[a] - e2[a]);
+}
+
+// Region node (x, y) of a tile (x in -1..nx, y in -1..ny): wrap periodic
+// sides.  Returns false when it lies beyond the frame or outside a
+// non-periodic side; gx, gy are always valid lattice coordinates (clamped
+// when false), so loads can be issued unconditionally.
+__device__ __forceinline__ bool region_coords(const Geom& g, int x, int y, int& gx, int& gy) {
+  bool ok = x >= -1 && x <= g.nx && y >= -1 && y <= g.ny;
+  gx = x;
+  gy = y;
+  if (gx < 0 || gx >= g.nx) {
+    if (g.side[kW] == kPeriodic) gx = gx < 0 ? gx + g.nx : gx - g.nx;
+    else ok = false;
   }
-  if (any) {
-    C d2[9];
-    bool dummy = false;
-#pragma unroll
-    for (int a = 0; a < 9; ++a) d2[a] = pull_general<S>(fa, solid, g, k, a, g.nx - 2, y, &dummy);
-    C r2, u2, v2;
-    macro<C>(d2, k, r2, u2, v2);
-    const C U = k.u_in_max;
-    const C invU = C(1) / (C(1) + U);
-    us = (hist_in[y] + U * u2) * invU;
-    vs = (hist_in[g.ny + y] + U * v2) * invU;
-    C e2[9], eo[9];
-    equilibrium_dev<C>(r2, u2, v2, k, e2);
-    equilibrium_dev<C>(C(0), us, vs, k, eo);
-#pragma unroll
-    for (int a = 0; a < 9; ++a)
-      if (outl[a]) d[a] = eo[a] + (d2[a] - e2[a]);
+  if (gy < 0 || gy >= g.ny) {
+    if (g.side[kS] == kPeriodic) gy = gy < 0 ? gy + g.ny : gy - g.ny;
+    else ok = false;
   }
-  return any;
+  gx = gx < 0 ? 0 : (gx >= g.nx ? g.nx - 1 : gx);
+  gy = gy < 0 ? 0 : (gy >= g.ny ? g.ny - 1 : gy);
+  return ok;
+}
+
+// Same, also false on a solid node (one dependent mask load).
+__device__ __forceinline__ bool region_node(const Geom& g, const uint8_t* __restrict__ solid,
+                                            int x, int y, int& gx, int& gy) {
+  if (!region_coords(g, x, y, gx, gy)) return false;
+  return !(solid && solid[(long long)gy * g.nx + gx]);
+}
+
+// Boundary links owned by fluid node (x, y), written into the destination
+// lattice after its collision (post-collision deviations d):
+//  - half-way bounce-back (eq. 2b with a wall, lid or inlet at the source):
+//    the link alpha from a non-fluid source s = x - e_alpha is pulled next step
+//    from slot (s, alpha), which receives d_opp(alpha) plus the moving-wall
+//    term 6 w_alpha rho0 (e_alpha . u_w) (lid: tangential u_lid; inlet:
+//    parabolic profile at this node's y; corner links: stationary);
+//  - periodic sides: the population that leaves across a periodic side is
+//    copied to the frame slot its wrapped target pulls from.
+// nonfluid(a) tells whether the source of link a is solid or outside a
+// non-periodic side.
+template <class S, class NF>
+__device__ __forceinline__ void ghost_writes(typename S::T* __restrict__ fb, const Geom& g,
+                                             const Consts<typename S::C>& k, int x, int y,
+                                             const typename S::C d[9], NF nonfluid) {
+  using C = typename S::C;
+  const bool px = g.side[kW] == kPeriodic, py = g.side[kS] == kPeriodic;
+#pragma unroll
+  for (int a = 1; a < 9; ++a) {
+    const int ex = ex_of(a), ey = ey_of(a);
+    // bounce-back family
+    if (nonfluid(a)) {
+      const int sx = x - ex, sy = y - ey;
+      const bool xo = (sx < 0 || sx >= g.nx) && !px;
+      const bool yo = (sy < 0 || sy >= g.ny) && !py;
+      C corr = C(0);
+      bool write = true;
+      if (xo != yo) {
+        const int sd = xo ? (sx < 0 ? kW : kE) : (sy < 0 ? kS : kN);
+        const int kind = g.side[sd];
+        if (kind == kOutlet) {
+          write = false;
+        } else if (kind == kLid) {
+          const C uw = k.u_lid;
+          corr = C(6) * w_of<C>(a) * k.rho0 * ((sd == kS || sd == kN) ? C(ex) : C(ey)) * uw;
+        } else if (kind == kInlet) {
+          const C H = C(g.ny), yy = C(y) + C(0.5);
+          const C uin = C(4) * k.u_in_max * yy * (H - yy) / (H * H);
+          corr = C(6) * w_of<C>(a) * k.rho0 * C(ex) * uin;
+        }
+      }
+      if (write)
+        fb[(long long)a * g.plane + gidx(g, sx, sy)] = S::enc(d[opp_of(a)] + corr, k.scale);
+    }
+    // periodic copy
+    if (px || py) {
+      int tx = x + ex, ty = y + ey;
+      bool cross = false, valid = true;
+      if (tx < 0 || tx >= g.nx) {
+        if (px) { tx = tx < 0 ? tx + g.nx : tx - g.nx; cross = true; } else valid = false;
+      }
+      if (ty < 0 || ty >= g.ny) {
+        if (py) { ty = ty < 0 ? ty + g.ny : ty - g.ny; cross = true; } else valid = false;
+      }
+      if (cross && valid)
+        fb[(long long)a * g.plane + gidx(g, tx - ex, ty - ey)] = S::enc(d[a], k.scale);
+    }
+  }
 }
 
 }  // namespace lbmk

@@ -3,20 +3,25 @@
 #pragma once
 
 // Fused stream-collide step of the GI-corrected preconditioned cascaded
-// D2Q9 LBM for gfx950, and the single-lattice C ABI declared in include/lbm.h.
+// D2Q9 LBM for gfx950.
 //
-// Kernel layout.  A block is 64 x BY threads (BY wave64 wavefronts); each
-// thread owns R consecutive lattice rows of one column.  The block's region is
-// 64 columns x (BY*R) rows; its outer ring (first/last lane, first/last row)
-// is a halo that is pulled and summed to rho but not collided, so the output
-// tile is 62 x (BY*R - 2) and neighbouring tiles overlap by two columns/rows.
-// Phase 1 pulls the nine populations of every region node (coalesced loads of
-// 64 consecutive x per population), writes rho - rho0 to LDS and keeps the
-// populations in registers; after one barrier, phase 2 takes the isotropic
-// density gradient from LDS, collides and stores the nine populations with
-// coalesced stores.  Halo re-reads are served by L2: one HBM read and one HBM
-// write of each population per step.  Tiles whose region and sources are
-// inside the lattice with no solid node skip every boundary test.
+// Kernel layout.  A block is 64 x BY threads (BY wave64 wavefronts) and owns
+// one tile of 64 columns x (BY*R - 2) rows; each thread holds R consecutive
+// rows of one column.  The block's region adds one halo row above and below
+// (pulled by the first/last row of threads) and one halo column left and
+// right (pulled by lanes 0 and 63), so that the density gradient at the same
+// time level needs no second pass.  Phase 1 pulls the nine populations of
+// every region node through the ghost frame (nine independent coalesced
+// loads, no boundary logic), writes rho - rho0 to LDS (a sentinel for solid
+// or outside nodes) and keeps the populations in registers; after one
+// barrier, phase 2 takes the density gradient from LDS, collides, stores the
+// nine populations with coalesced full-line stores and, on boundary nodes
+// only, writes the bounce-back and periodic values into the ghost/solid slots
+// of the destination lattice.  The outlet column is the one node set with
+// extra work (non-equilibrium extrapolation from column nx-2).  Halo re-reads
+// are served by L2: one HBM read and one HBM write of each population per
+// step.  Tiles are mapped to blocks XCD by XCD so that neighbouring tiles
+// share an L2.
 //
 // Check steps also accumulate in FP64, per block, sum |u^{n+1}-u^n|^2,
 // sum |u^n|^2, sum (rho - rho0) and the guard count (wavefront shuffles, then
@@ -36,15 +41,13 @@
 namespace lbmk {
 
 constexpr int kLanes = 64;
-constexpr int kOutX = kLanes - 2;
 
 enum Flavor : int { kPlain = 0, kStore = 1, kCheck = 2 };
 
 struct StepArgs {
   Geom g;
   int tiles_x, ntiles, out_rows;
-  const uint8_t* solid;   // nullptr when the lattice has no solid node
-  const uint8_t* tile_fast;
+  const uint8_t* solid;   // [ny][nx], nullptr when the lattice has no solid node
   const void* hist_in;    // outlet history [2][ny] (compute type)
   void* hist_out;
   void* ubuf;             // [2][ny][nx] previous velocity (compute type)
@@ -67,148 +70,176 @@ __device__ __forceinline__ C wave_sum(C v) {
   return v;
 }
 
-template <class S, int BY, int R, int FL>
+template <class C>
+__device__ __forceinline__ C sum9(const C d[9]) {
+  return ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
+}
+
+// Per-node epilogue: store populations, velocity buffer and residual partials.
+// li: index in the (framed) lattice; fi: index in the nx*ny field arrays.
+template <class S, int FL>
+__device__ __forceinline__ void finish_node(typename S::T* __restrict__ fb, const StepArgs& args,
+                                            const Consts<typename S::C>& k, const typename S::C d[9],
+                                            long long li, long long fi, typename S::C drho,
+                                            typename S::C ux, typename S::C uy, int guarded,
+                                            double acc[4]) {
+  using C = typename S::C;
+  const Geom& g = args.g;
+#pragma unroll
+  for (int a = 0; a < 9; ++a) fb[(long long)a * g.plane + li] = S::enc(d[a], k.scale);
+  C* ubuf = static_cast<C*>(args.ubuf);
+  const long long np = (long long)g.nx * g.ny;
+  if (FL == kCheck) {
+    const double px = ubuf[fi], py = ubuf[np + fi];
+    const double dx = double(ux) - px, dy = double(uy) - py;
+    acc[0] += dx * dx + dy * dy;
+    acc[1] += px * px + py * py;
+    acc[2] += double(drho);
+    acc[3] += double(guarded);
+  }
+  if (FL == kStore || FL == kCheck) {
+    ubuf[fi] = ux;
+    ubuf[np + fi] = uy;
+  }
+}
+
+// Check-step partials of one block: wavefront shuffles, then LDS.
+template <int BY>
+__device__ __forceinline__ void block_partials(double acc[4], double (*s_red)[4], int lane, int w,
+                                               double* __restrict__ out) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) acc[i] = wave_sum(acc[i]);
+  if (lane == 0)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s_red[w][i] = acc[i];
+  __syncthreads();
+  if (lane < 4 && w == 0) {
+    double t = 0.0;
+    for (int i = 0; i < BY; ++i) t += s_red[i][lane];
+    out[lane] = t;
+  }
+}
+
+template <class S, int BY, int R, int FL, bool OBST, bool OUTL>
 __global__ __launch_bounds__(kLanes* BY) void step_kernel(const typename S::T* __restrict__ fa,
                                                           typename S::T* __restrict__ fb,
                                                           const StepArgs args,
                                                           const Consts<typename S::C> k) {
   using C = typename S::C;
-  using T = typename S::T;
   constexpr int RR = BY * R;  // region rows
-  __shared__ C s_rho[RR][kLanes];
+  constexpr int W = kLanes + 2;
+  const C SENT = C(HUGE_VALF);
+  __shared__ C s_rho[RR][W];
   __shared__ double s_red[BY][4];
-
   const Geom& g = args.g;
   const int lane = threadIdx.x;
   const int w = threadIdx.y;
   const int tile = xcd_tile(blockIdx.x, args.ntiles);
   const int tx = tile % args.tiles_x;
   const int ty = tile / args.tiles_x;
-  const int x = tx * kOutX - 1 + lane;
+  const int x = tx * kLanes + lane;
   const int y0 = ty * args.out_rows - 1 + w * R;
-  const bool fast = args.tile_fast[tile] != 0;
+  const bool halo_lane = lane == 0 || lane == kLanes - 1;
+  const int hx = lane == 0 ? x - 1 : x + 1;
+  const int hc = lane == 0 ? 0 : W - 1;
   const C* hist_in = static_cast<const C*>(args.hist_in);
 
-  C d[R][9];
-  bool live[R];  // fluid node whose rho was computed
-  C us_r[R], vs_r[R];
-  bool outl_r[R];
-
+  // ---- phase 1: one batch of loads (main node, halo column, mask bytes),
+  // then rho - rho0 to LDS (sentinel for solid / outside nodes)
+  C d[R][9], dh[R][9];
+  C us[R], vs[R];
+  bool ok[R], hok[R];
+  int gxr[R], gyr[R], hgx[R], hgy[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int y = y0 + r;
-    live[r] = false;
-    outl_r[r] = false;
-    C drho = C(0);
-    if (fast) {
-      // region and every source inside the lattice, all fluid
-      const long long own = (long long)y * g.nx + x;
+    ok[r] = region_coords(g, x, y, gxr[r], gyr[r]);
+    hok[r] = halo_lane && region_coords(g, hx, y, hgx[r], hgy[r]);
+    pull9<S>(fa, g, k, gxr[r], gyr[r], d[r]);
+    if (halo_lane) pull9<S>(fa, g, k, hgx[r], hgy[r], dh[r]);
+    if (OBST) {
+      ok[r] = ok[r] && !args.solid[(long long)gyr[r] * g.nx + gxr[r]];
+      if (halo_lane) hok[r] = hok[r] && !args.solid[(long long)hgy[r] * g.nx + hgx[r]];
+    }
+  }
+  if (OUTL) {
 #pragma unroll
-      for (int a = 0; a < 9; ++a)
-        d[r][a] = S::dec(fa[(long long)a * g.plane + own - ex_of(a) - (long long)ey_of(a) * g.nx],
-                         k.inv_scale);
-      live[r] = true;
-    } else if (x >= -1 && x <= g.nx && y >= -1 && y <= g.ny) {
-      int gx = x, gy = y;
-      bool ok = true;
-      if (gx < 0 || gx >= g.nx) {
-        if (g.side[gx < 0 ? kW : kE] == kPeriodic) gx = gx < 0 ? gx + g.nx : gx - g.nx;
-        else ok = false;
-      }
-      if (gy < 0 || gy >= g.ny) {
-        if (g.side[gy < 0 ? kS : kN] == kPeriodic) gy = gy < 0 ? gy + g.ny : gy - g.ny;
-        else ok = false;
-      }
-      if (ok && args.solid && args.solid[(long long)gy * g.nx + gx]) ok = false;
-      if (ok) {
-        outl_r[r] = pull_node_general<S>(fa, args.solid, g, k, hist_in, gx, gy, d[r], us_r[r],
-                                         vs_r[r]);
-        live[r] = true;
+    for (int r = 0; r < R; ++r) {
+      if (ok[r] && gxr[r] == g.nx - 1) outlet_links<S>(fa, g, k, hist_in, gyr[r], d[r], us[r], vs[r]);
+      if (hok[r] && hgx[r] == g.nx - 1) {
+        C a_, b_;
+        outlet_links<S>(fa, g, k, hist_in, hgy[r], dh[r], a_, b_);
       }
     }
-    if (live[r]) {
-      drho = ((d[r][0] + d[r][1]) + (d[r][2] + d[r][3])) +
-             ((d[r][4] + d[r][5]) + (d[r][6] + d[r][7])) + d[r][8];
-    }
-    s_rho[w * R + r][lane] = live[r] ? drho : C(HUGE_VALF);
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    s_rho[w * R + r][lane + 1] = ok[r] ? sum9<C>(d[r]) : SENT;
+    if (halo_lane) s_rho[w * R + r][hc] = hok[r] ? sum9<C>(dh[r]) : SENT;
   }
   __syncthreads();
 
-  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-  C* ubuf = static_cast<C*>(args.ubuf);
+  // ---- phase 2: gradient, collision, stores, boundary slots
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int ry = w * R + r;
     const int y = y0 + r;
-    const bool out = live[r] && lane >= 1 && lane <= kOutX && ry >= 1 && ry <= RR - 2 &&
-                     x < g.nx && y < g.ny;
-    if (!out) continue;
-    const C own = s_rho[ry][lane];
-    auto nb = [&](int dy, int dx) -> C {
-      const C v = s_rho[ry + dy][lane + dx];
-      return v == C(HUGE_VALF) ? own : v;
-    };
+    if (ry < 1 || ry > RR - 2 || x >= g.nx || y >= g.ny) continue;
+    const int c = lane + 1;
+    const C own = s_rho[ry][c];
+    if (own == SENT) continue;  // solid node
+    // the eight neighbours, sentinel = solid or outside a non-periodic side
+    const C nE = s_rho[ry][c + 1], nW = s_rho[ry][c - 1];
+    const C nN = s_rho[ry + 1][c], nS = s_rho[ry - 1][c];
+    const C nNE = s_rho[ry + 1][c + 1], nNW = s_rho[ry + 1][c - 1];
+    const C nSE = s_rho[ry - 1][c + 1], nSW = s_rho[ry - 1][c - 1];
+    auto sub = [&](C v) { return v == SENT ? own : v; };
     C drx, dry;
     if (k.stencil == 0) {
       // isotropic: d rho = 3 sum_a w_a e_a rho(x + e_a)
-      const C ne = nb(1, 1), nw = nb(1, -1), se = nb(-1, 1), sw = nb(-1, -1);
-      drx = (nb(0, 1) - nb(0, -1)) * (C(1) / C(3)) + ((ne - nw) + (se - sw)) * (C(1) / C(12));
-      dry = (nb(1, 0) - nb(-1, 0)) * (C(1) / C(3)) + ((ne - se) + (nw - sw)) * (C(1) / C(12));
+      const C ne = sub(nNE), nw = sub(nNW), se = sub(nSE), sw = sub(nSW);
+      drx = (sub(nE) - sub(nW)) * (C(1) / C(3)) + ((ne - nw) + (se - sw)) * (C(1) / C(12));
+      dry = (sub(nN) - sub(nS)) * (C(1) / C(3)) + ((ne - se) + (nw - sw)) * (C(1) / C(12));
     } else {
-      drx = C(0.5) * (nb(0, 1) - nb(0, -1));
-      dry = C(0.5) * (nb(1, 0) - nb(-1, 0));
+      drx = C(0.5) * (sub(nE) - sub(nW));
+      dry = C(0.5) * (sub(nN) - sub(nS));
     }
     C drho, ux, uy;
     const int gd = collide<C>(d[r], drx, dry, k, drho, ux, uy);
-    const long long own_i = (long long)y * g.nx + x;
-#pragma unroll
-    for (int a = 0; a < 9; ++a) fb[(long long)a * g.plane + own_i] = S::enc(d[r][a], k.scale);
-    if (outl_r[r]) {
+    finish_node<S, FL>(fb, args, k, d[r], gidx(g, x, y), (long long)y * g.nx + x, drho, ux, uy,
+                       gd, acc);
+    // boundary links: source of link a is the neighbour at -e_a
+    const bool any_nf = (nE == SENT) | (nW == SENT) | (nN == SENT) | (nS == SENT) |
+                        (nNE == SENT) | (nNW == SENT) | (nSE == SENT) | (nSW == SENT);
+    const bool edge = x == 0 || x == g.nx - 1 || y == 0 || y == g.ny - 1;
+    if (any_nf || edge) {
+      auto nonfluid = [&](int a) {
+        const int sx = -ex_of(a), sy = -ey_of(a);
+        const C v = sy == 0 ? (sx > 0 ? nE : nW)
+                            : (sy > 0 ? (sx > 0 ? nNE : (sx < 0 ? nNW : nN))
+                                      : (sx > 0 ? nSE : (sx < 0 ? nSW : nS)));
+        return v == SENT;
+      };
+      ghost_writes<S>(fb, g, k, x, y, d[r], nonfluid);
+    }
+    if (OUTL && x == g.nx - 1) {
       C* ho = static_cast<C*>(args.hist_out);
-      ho[y] = us_r[r];
-      ho[g.ny + y] = vs_r[r];
-    }
-    if (FL == kCheck) {
-      const double px = ubuf[own_i], py = ubuf[g.plane + own_i];
-      const double dx = double(ux) - px, dy = double(uy) - py;
-      acc0 += dx * dx + dy * dy;
-      acc1 += px * px + py * py;
-      acc2 += double(drho);
-      acc3 += double(gd);
-    }
-    if (FL == kStore || FL == kCheck) {
-      ubuf[own_i] = ux;
-      ubuf[g.plane + own_i] = uy;
+      ho[y] = us[r];
+      ho[g.ny + y] = vs[r];
     }
   }
-  if (FL == kCheck) {
-    acc0 = wave_sum(acc0);
-    acc1 = wave_sum(acc1);
-    acc2 = wave_sum(acc2);
-    acc3 = wave_sum(acc3);
-    if (lane == 0) {
-      s_red[w][0] = acc0;
-      s_red[w][1] = acc1;
-      s_red[w][2] = acc2;
-      s_red[w][3] = acc3;
-    }
-    __syncthreads();
-    if (lane < 4 && w == 0) {
-      double t = 0.0;
-      for (int i = 0; i < BY; ++i) t += s_red[i][lane];
-      args.partials[(long long)tile * 4 + lane] = t;
-    }
-  }
+  if (FL == kCheck) block_partials<BY>(acc, s_red, lane, w, args.partials + (long long)tile * 4);
 }
 
-// Launch one fused step for a given storage type (defined in lbm_step_<type>.hip).
+// One fused step over all tiles (one block per tile).
 void launch_step_f64(int by, int rows, int flavor, const void* src, void* dst, const StepArgs& a,
-                     const Consts<double>& k, int ntiles, hipStream_t st);
+                     const Consts<double>& k, hipStream_t st);
 void launch_step_f32(int by, int rows, int flavor, const void* src, void* dst, const StepArgs& a,
-                     const Consts<float>& k, int ntiles, hipStream_t st);
+                     const Consts<float>& k, hipStream_t st);
 void launch_step_bf16(int by, int rows, int flavor, const void* src, void* dst, const StepArgs& a,
-                      const Consts<float>& k, int ntiles, hipStream_t st);
+                      const Consts<float>& k, hipStream_t st);
 void launch_step_f16(int by, int rows, int flavor, const void* src, void* dst, const StepArgs& a,
-                     const Consts<float>& k, int ntiles, hipStream_t st);
+                     const Consts<float>& k, hipStream_t st);
 
 }  // namespace lbmk
