@@ -69,8 +69,8 @@ __global__ __launch_bounds__(256) void init_kernel(typename S::T* __restrict__ f
 #pragma unroll
   for (int a = 0; a < 9; ++a) {
     const typename S::T v = S::enc(f[a], k.scale);
-    fa[a * g.plane + li] = v;
-    fb[a * g.plane + li] = v;
+    fa[(long long)a * g.plane + li] = v;
+    fb[(long long)a * g.plane + li] = v;
   }
   ubuf[i] = vx;
   ubuf[np + i] = vy;
@@ -170,7 +170,7 @@ int fail(int code, const std::string& msg) {
 struct Shape {
   int by, rows;
 };
-constexpr Shape kShapes[] = {{16, 1}, {8, 1}, {4, 2}, {8, 2}, {16, 2}, {4, 4}, {8, 4}};
+constexpr Shape kShapes[] = {{16, 1}, {8, 1}, {4, 1}, {4, 2}, {8, 2}, {4, 4}, {8, 4}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
 size_t storage_bytes(int storage) {
@@ -266,7 +266,7 @@ Geom make_geom_for(int nx, int ny, const int32_t side[4], size_t esize) {
   const int line = int(128 / esize);  // elements per 128-byte line
   g.padx = line;
   g.pitch = ((nx + 2 * line) + line - 1) / line * line;
-  g.plane = (long long)g.pitch * (ny + 2);
+  g.plane = g.pitch * (ny + 2);
   return g;
 }
 
@@ -275,8 +275,12 @@ Geom make_geom(const lbm_ctx* c) { return make_geom_for(c->grid.nx, c->grid.ny, 
 int validate(const lbm_grid* grid, const uint8_t* solid, const lbm_params* p) {
   if (!grid || !p) return fail(LBM_EINVAL, "null grid or params");
   if (grid->nx < 2 || grid->ny < 2) return fail(LBM_EINVAL, "nx and ny must be >= 2");
-  if ((long long)grid->nx * grid->ny > (1LL << 31))
-    return fail(LBM_EINVAL, "lattice too large (more than 2^31 nodes)");
+  {
+    const long long pitch = grid->nx + 2 * 64 + 64;
+    if (9LL * pitch * (grid->ny + 2) >= (1LL << 31))
+      return fail(LBM_EINVAL, "lattice too large (9 framed planes must hold fewer than 2^31 "
+                              "elements)");
+  }
   for (int s = 0; s < 4; ++s)
     if (grid->side[s] < LBM_SIDE_PERIODIC || grid->side[s] > LBM_SIDE_OUTLET)
       return fail(LBM_EINVAL, "unknown side kind");
@@ -304,8 +308,7 @@ int validate(const lbm_grid* grid, const uint8_t* solid, const lbm_params* p) {
 }
 
 int configure_tiles(lbm_ctx* c) {
-  const int rr = c->by * c->rows;
-  c->out_rows = rr - 2;
+  c->out_rows = c->by * c->rows;
   c->tiles_x = (c->grid.nx + kLanes - 1) / kLanes;
   c->tiles_y = (c->grid.ny + c->out_rows - 1) / c->out_rows;
   c->ntiles = c->tiles_x * c->tiles_y;

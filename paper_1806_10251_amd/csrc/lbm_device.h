@@ -99,12 +99,19 @@ struct Geom {
   int side[4];
   int pitch;        // stored elements per row
   int padx;         // offset of column 0 within a stored row
-  long long plane;  // pitch * (ny + 2)
+  int plane;  // pitch * (ny + 2); 9 * plane < 2^31
 };
 
-__host__ __device__ __forceinline__ long long gidx(const Geom& g, int x, int y) {
-  return (long long)(y + 1) * g.pitch + g.padx + x;
+// Element offsets within a plane and across the nine planes fit in 32 bits
+// (enforced at creation), so loads and stores use a 64-bit base plus a
+// 32-bit offset.
+__host__ __device__ __forceinline__ int gidx(const Geom& g, int x, int y) {
+  return (y + 1) * g.pitch + g.padx + x;
 }
+
+// Reciprocal: hardware v_rcp_f32 (1 ulp) in FP32, correctly rounded in FP64.
+__device__ __forceinline__ float rcp(float v) { return __builtin_amdgcn_rcpf(v); }
+__device__ __forceinline__ double rcp(double v) { return 1.0 / v; }
 
 // ---------------------------------------------------------------------------
 // Equilibrium deviation f^eq - w rho0 at (rho0 + drho, u): the Sec. 3 raw
@@ -155,7 +162,7 @@ __device__ __forceinline__ void macro(const C d[9], const Consts<C>& k, C& drho,
     jx += C(0.5) * k.fx * k.ig;
     jy += C(0.5) * k.fy * k.ig;
   }
-  const C inv = C(1) / (k.rho0 + drho);
+  const C inv = rcp(k.rho0 + drho);
   ux = jx * inv;
   uy = jy * inv;
 }
@@ -184,7 +191,7 @@ __device__ __forceinline__ int collide(C d[9], C drx, C dry, const Consts<C>& k,
     jy += C(0.5) * k.fy * k.ig;
   }
   const C rho = k.rho0 + drho;
-  const C inv_rho = C(1) / rho;
+  const C inv_rho = rcp(rho);
   const C ux = jx * inv_rho, uy = jy * inv_rho;
   const C ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
   // source raw moments sigma' (Sec. 3); moments below are those of f = fbar + S/2
@@ -233,7 +240,7 @@ __device__ __forceinline__ int collide(C d[9], C drx, C dry, const Consts<C>& k,
       guarded = 1;
     }
     const C R3 = m3 - er, R4 = m4 - ert;
-    const C invD = C(1) / D;
+    const C invD = rcp(D);
     const C dxux = (ct2 * R3 + c2 * R4) * invD;
     const C dyuy = (ct1 * R3 - c1 * R4) * invD;
     // extended-equilibrium corrections, eqs. 33 with 45-47
@@ -296,11 +303,10 @@ template <class S>
 __device__ __forceinline__ void pull9(const typename S::T* __restrict__ fa, const Geom& g,
                                       const Consts<typename S::C>& k, int x, int y,
                                       typename S::C d[9]) {
-  const long long own = gidx(g, x, y);
+  const int own = gidx(g, x, y);
 #pragma unroll
   for (int a = 0; a < 9; ++a)
-    d[a] = S::dec(fa[(long long)a * g.plane + own - ex_of(a) - (long long)ey_of(a) * g.pitch],
-                  k.inv_scale);
+    d[a] = S::dec(fa[a * g.plane + own - ex_of(a) - ey_of(a) * g.pitch], k.inv_scale);
 }
 
 // Links of node (nx-1, y) that cross an OUTLET side (e_x = -1, source not a
@@ -410,7 +416,7 @@ __device__ __forceinline__ void ghost_writes(typename S::T* __restrict__ fb, con
         }
       }
       if (write)
-        fb[(long long)a * g.plane + gidx(g, sx, sy)] = S::enc(d[opp_of(a)] + corr, k.scale);
+        fb[a * g.plane + gidx(g, sx, sy)] = S::enc(d[opp_of(a)] + corr, k.scale);
     }
     // periodic copy
     if (px || py) {
@@ -423,7 +429,7 @@ __device__ __forceinline__ void ghost_writes(typename S::T* __restrict__ fb, con
         if (py) { ty = ty < 0 ? ty + g.ny : ty - g.ny; cross = true; } else valid = false;
       }
       if (cross && valid)
-        fb[(long long)a * g.plane + gidx(g, tx - ex, ty - ey)] = S::enc(d[a], k.scale);
+        fb[a * g.plane + gidx(g, tx - ex, ty - ey)] = S::enc(d[a], k.scale);
     }
   }
 }

@@ -80,15 +80,15 @@ __device__ __forceinline__ C sum9(const C d[9]) {
 template <class S, int FL>
 __device__ __forceinline__ void finish_node(typename S::T* __restrict__ fb, const StepArgs& args,
                                             const Consts<typename S::C>& k, const typename S::C d[9],
-                                            long long li, long long fi, typename S::C drho,
+                                            int li, int fi, typename S::C drho,
                                             typename S::C ux, typename S::C uy, int guarded,
                                             double acc[4]) {
   using C = typename S::C;
   const Geom& g = args.g;
 #pragma unroll
-  for (int a = 0; a < 9; ++a) fb[(long long)a * g.plane + li] = S::enc(d[a], k.scale);
+  for (int a = 0; a < 9; ++a) fb[a * g.plane + li] = S::enc(d[a], k.scale);
   C* ubuf = static_cast<C*>(args.ubuf);
-  const long long np = (long long)g.nx * g.ny;
+  const int np = g.nx * g.ny;
   if (FL == kCheck) {
     const double px = ubuf[fi], py = ubuf[np + fi];
     const double dx = double(ux) - px, dy = double(uy) - py;
@@ -126,7 +126,8 @@ __global__ __launch_bounds__(kLanes* BY) void step_kernel(const typename S::T* _
                                                           const StepArgs args,
                                                           const Consts<typename S::C> k) {
   using C = typename S::C;
-  constexpr int RR = BY * R;  // region rows
+  constexpr int RO = BY * R;   // output rows of the tile
+  constexpr int RR = RO + 2;   // region rows (one halo row above and below)
   constexpr int W = kLanes + 2;
   const C SENT = C(HUGE_VALF);
   __shared__ C s_rho[RR][W];
@@ -138,14 +139,38 @@ __global__ __launch_bounds__(kLanes* BY) void step_kernel(const typename S::T* _
   const int tx = tile % args.tiles_x;
   const int ty = tile / args.tiles_x;
   const int x = tx * kLanes + lane;
-  const int y0 = ty * args.out_rows - 1 + w * R;
+  const int ytile = ty * RO;        // first output row of the tile
+  const int y0 = ytile + w * R;     // this thread's first row
   const bool halo_lane = lane == 0 || lane == kLanes - 1;
   const int hx = lane == 0 ? x - 1 : x + 1;
   const int hc = lane == 0 ? 0 : W - 1;
   const C* hist_in = static_cast<const C*>(args.hist_in);
 
-  // ---- phase 1: one batch of loads (main node, halo column, mask bytes),
-  // then rho - rho0 to LDS (sentinel for solid / outside nodes)
+  // rho - rho0 of one region row (main lane and, on lanes 0/63, the halo
+  // column) into LDS row lr; used for the two halo rows
+  auto halo_row = [&](int y, int lr) {
+    int gx, gy, hgx, hgy;
+    bool ok = region_coords(g, x, y, gx, gy);
+    bool hok = halo_lane && region_coords(g, hx, y, hgx, hgy);
+    C dm[9], dh[9];
+    pull9<S>(fa, g, k, gx, gy, dm);
+    if (halo_lane) pull9<S>(fa, g, k, hgx, hgy, dh);
+    if (OBST) {
+      ok = ok && !args.solid[gy * g.nx + gx];
+      if (halo_lane) hok = hok && !args.solid[hgy * g.nx + hgx];
+    }
+    if (OUTL) {
+      C a_, b_;
+      if (ok && gx == g.nx - 1) outlet_links<S>(fa, g, k, hist_in, gy, dm, a_, b_);
+      if (hok && hgx == g.nx - 1) outlet_links<S>(fa, g, k, hist_in, hgy, dh, a_, b_);
+    }
+    s_rho[lr][lane + 1] = ok ? sum9<C>(dm) : SENT;
+    if (halo_lane) s_rho[lr][hc] = hok ? sum9<C>(dh) : SENT;
+  };
+
+  // ---- phase 1: one batch of loads per row (main node, halo column, mask),
+  // then rho - rho0 to LDS (sentinel for solid / outside nodes).  The first
+  // and the last wavefront also pull the halo rows.
   C d[R][9], dh[R][9];
   C us[R], vs[R];
   bool ok[R], hok[R];
@@ -158,10 +183,12 @@ __global__ __launch_bounds__(kLanes* BY) void step_kernel(const typename S::T* _
     pull9<S>(fa, g, k, gxr[r], gyr[r], d[r]);
     if (halo_lane) pull9<S>(fa, g, k, hgx[r], hgy[r], dh[r]);
     if (OBST) {
-      ok[r] = ok[r] && !args.solid[(long long)gyr[r] * g.nx + gxr[r]];
-      if (halo_lane) hok[r] = hok[r] && !args.solid[(long long)hgy[r] * g.nx + hgx[r]];
+      ok[r] = ok[r] && !args.solid[gyr[r] * g.nx + gxr[r]];
+      if (halo_lane) hok[r] = hok[r] && !args.solid[hgy[r] * g.nx + hgx[r]];
     }
   }
+  if (w == 0) halo_row(ytile - 1, 0);
+  if (w == BY - 1) halo_row(ytile + RO, RR - 1);
   if (OUTL) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -174,8 +201,8 @@ __global__ __launch_bounds__(kLanes* BY) void step_kernel(const typename S::T* _
   }
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    s_rho[w * R + r][lane + 1] = ok[r] ? sum9<C>(d[r]) : SENT;
-    if (halo_lane) s_rho[w * R + r][hc] = hok[r] ? sum9<C>(dh[r]) : SENT;
+    s_rho[w * R + r + 1][lane + 1] = ok[r] ? sum9<C>(d[r]) : SENT;
+    if (halo_lane) s_rho[w * R + r + 1][hc] = hok[r] ? sum9<C>(dh[r]) : SENT;
   }
   __syncthreads();
 
@@ -183,9 +210,9 @@ __global__ __launch_bounds__(kLanes* BY) void step_kernel(const typename S::T* _
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int ry = w * R + r;
+    const int ry = w * R + r + 1;  // LDS row
     const int y = y0 + r;
-    if (ry < 1 || ry > RR - 2 || x >= g.nx || y >= g.ny) continue;
+    if (x >= g.nx || y >= g.ny) continue;
     const int c = lane + 1;
     const C own = s_rho[ry][c];
     if (own == SENT) continue;  // solid node
@@ -207,7 +234,7 @@ __global__ __launch_bounds__(kLanes* BY) void step_kernel(const typename S::T* _
     }
     C drho, ux, uy;
     const int gd = collide<C>(d[r], drx, dry, k, drho, ux, uy);
-    finish_node<S, FL>(fb, args, k, d[r], gidx(g, x, y), (long long)y * g.nx + x, drho, ux, uy,
+    finish_node<S, FL>(fb, args, k, d[r], gidx(g, x, y), y * g.nx + x, drho, ux, uy,
                        gd, acc);
     // boundary links: source of link a is the neighbour at -e_a
     const bool any_nf = (nE == SENT) | (nW == SENT) | (nN == SENT) | (nS == SENT) |

@@ -40,9 +40,9 @@ void launch_step_f32(int by, int rows, int flavor, const void* src, void* dst,
   switch (by * 100 + rows) {
     case 1601: go<16, 1>(flavor, obst, outl, src, dst, a, k, st); break;
     case 801: go<8, 1>(flavor, obst, outl, src, dst, a, k, st); break;
+    case 401: go<4, 1>(flavor, obst, outl, src, dst, a, k, st); break;
     case 402: go<4, 2>(flavor, obst, outl, src, dst, a, k, st); break;
     case 802: go<8, 2>(flavor, obst, outl, src, dst, a, k, st); break;
-    case 1602: go<16, 2>(flavor, obst, outl, src, dst, a, k, st); break;
     case 404: go<4, 4>(flavor, obst, outl, src, dst, a, k, st); break;
     default: go<8, 4>(flavor, obst, outl, src, dst, a, k, st); break;
   }
