@@ -14,158 +14,28 @@
 #include <vector>
 
 #include "../../include/lbm.h"
+#include "lbm_aux.h"
+#include "lbm_host.h"
 #include "lbm_kernels.h"
 
 using namespace lbmk;
+using namespace lbmh;
 
+namespace lbmh {
 namespace {
-
-// Fixed-order sum of the per-tile partials: out[0..3].
-__global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict__ partials,
-                                                       int n, double* __restrict__ out) {
-  __shared__ double s[4][256];
-  const int t = threadIdx.x;
-  double a[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int i = t; i < n; i += 256)
-    for (int c = 0; c < 4; ++c) a[c] += partials[(long long)i * 4 + c];
-  for (int c = 0; c < 4; ++c) s[c][t] = a[c];
-  __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if (t < h)
-      for (int c = 0; c < 4; ++c) s[c][t] += s[c][t + h];
-    __syncthreads();
-  }
-  if (t < 4) out[t] = s[t][0];
-}
-
-// Equilibrium initialisation from optional device fields; also writes the
-// velocity buffer and the outlet history.  Interior nodes of both lattices.
-template <class S, class FT>
-__global__ __launch_bounds__(256) void init_kernel(typename S::T* __restrict__ fa,
-                                                   typename S::T* __restrict__ fb, Geom g,
-                                                   Consts<typename S::C> k,
-                                                   const uint8_t* __restrict__ solid,
-                                                   const FT* __restrict__ rho,
-                                                   const FT* __restrict__ ux,
-                                                   const FT* __restrict__ uy,
-                                                   typename S::C* __restrict__ ubuf,
-                                                   typename S::C* __restrict__ hist0,
-                                                   typename S::C* __restrict__ hist1) {
-  using C = typename S::C;
-  const long long np = (long long)g.nx * g.ny;
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= np) return;
-  const bool sol = solid && solid[i];
-  C drho = C(0), vx = C(0), vy = C(0);
-  if (!sol) {
-    if (rho) drho = C(rho[i]) - k.rho0;
-    if (ux) vx = C(ux[i]);
-    if (uy) vy = C(uy[i]);
-  }
-  C f[9];
-  equilibrium_dev<C>(drho, vx, vy, k, f);
-  const int x = int(i % g.nx), y = int(i / g.nx);
-  const long long li = gidx(g, x, y);
-#pragma unroll
-  for (int a = 0; a < 9; ++a) {
-    const typename S::T v = S::enc(f[a], k.scale);
-    fa[(long long)a * g.plane + li] = v;
-    fb[(long long)a * g.plane + li] = v;
-  }
-  ubuf[i] = vx;
-  ubuf[np + i] = vy;
-  if (x == g.nx - 1) {
-    hist0[y] = vx;
-    hist0[g.ny + y] = vy;
-    hist1[y] = vx;
-    hist1[g.ny + y] = vy;
-  }
-}
-
-// Boundary slots of a lattice from its own fluid-node values (after an
-// initialisation or a checkpoint load).
-template <class S>
-__global__ __launch_bounds__(256) void ghost_fill_kernel(typename S::T* __restrict__ fa, Geom g,
-                                                         Consts<typename S::C> k,
-                                                         const uint8_t* __restrict__ solid) {
-  using C = typename S::C;
-  const long long np = (long long)g.nx * g.ny;
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= np) return;
-  if (solid && solid[i]) return;
-  const int x = int(i % g.nx), y = int(i / g.nx);
-  C d[9];
-  const long long li = gidx(g, x, y);
-#pragma unroll
-  for (int a = 0; a < 9; ++a) d[a] = S::dec(fa[a * g.plane + li], k.inv_scale);
-  auto nonfluid = [&](int a) {
-    int gx, gy;
-    return !region_node(g, solid, x - ex_of(a), y - ey_of(a), gx, gy);
-  };
-  ghost_writes<S>(fa, g, k, x, y, d, nonfluid);
-}
-
-// Decode populations (full f) or macroscopic fields of the current lattice.
-template <class S>
-__global__ __launch_bounds__(256) void export_kernel(const typename S::T* __restrict__ fa, Geom g,
-                                                     Consts<typename S::C> k,
-                                                     const uint8_t* __restrict__ solid,
-                                                     double* __restrict__ pops,
-                                                     float* __restrict__ rho_o,
-                                                     float* __restrict__ ux_o,
-                                                     float* __restrict__ uy_o,
-                                                     double* __restrict__ rho_d,
-                                                     double* __restrict__ ux_d,
-                                                     double* __restrict__ uy_d) {
-  using C = typename S::C;
-  const long long np = (long long)g.nx * g.ny;
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= np) return;
-  const long long li = gidx(g, int(i % g.nx), int(i / g.nx));
-  C d[9];
-#pragma unroll
-  for (int a = 0; a < 9; ++a) d[a] = S::dec(fa[a * g.plane + li], k.inv_scale);
-  if (pops) {
-#pragma unroll
-    for (int a = 0; a < 9; ++a)
-      pops[a * np + i] = double(d[a]) + double(w_of<C>(a)) * double(k.rho0);
-  }
-  const bool sol = solid && solid[i];
-  // post-collision moments: rho is unchanged by collision; the momentum has
-  // received F/gamma, so u = (sum e f~ - F/(2 gamma)) / rho
-  C drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
-  C jx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
-  C jy = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
-  if (k.force) {
-    jx -= C(0.5) * k.fx * k.ig;
-    jy -= C(0.5) * k.fy * k.ig;
-  }
-  const C rho = k.rho0 + drho;
-  const C vx = jx / rho, vy = jy / rho;
-  if (rho_o) rho_o[i] = sol ? 0.f : float(rho);
-  if (ux_o) ux_o[i] = sol ? 0.f : float(vx);
-  if (uy_o) uy_o[i] = sol ? 0.f : float(vy);
-  if (rho_d) rho_d[i] = sol ? 0.0 : double(k.rho0) + double(drho);
-  if (ux_d) ux_d[i] = sol ? 0.0 : double(vx);
-  if (uy_d) uy_d[i] = sol ? 0.0 : double(vy);
-}
-
-// ---------------------------------------------------------------------------
-// Host side
-// ---------------------------------------------------------------------------
 thread_local std::string g_err;
-
+}
 int fail(int code, const std::string& msg) {
   g_err = msg;
   return code;
 }
+}  // namespace lbmh
 
-#define HIPCHECK(expr)                                                              \
-  do {                                                                              \
-    hipError_t e_ = (expr);                                                         \
-    if (e_ != hipSuccess)                                                           \
-      return fail(LBM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
-  } while (0)
+namespace {
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
 
 struct Shape {
   int by, rows;
@@ -173,13 +43,6 @@ struct Shape {
 constexpr Shape kShapes[] = {{16, 1}, {8, 1}, {4, 1}, {4, 2}, {8, 2}, {4, 4}, {8, 4}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
-size_t storage_bytes(int storage) {
-  switch (storage) {
-    case LBM_STORE_F64: return 8;
-    case LBM_STORE_F32: return 4;
-    default: return 2;
-  }
-}
 
 }  // namespace
 
@@ -222,90 +85,10 @@ const Consts<double>& consts_for<double>(const lbm_ctx* c) { return c->kd; }
 template <>
 const Consts<float>& consts_for<float>(const lbm_ctx* c) { return c->kf; }
 
-template <class C>
-Consts<C> make_consts(const lbm_params& p, double scale) {
-  const double g = p.gamma;
-  const double w4 = 1.0 / (3.0 * p.nu / g + 0.5);
-  Consts<C> k{};
-  k.rho0 = C(p.rho0);
-  k.ig = C(1.0 / g);
-  k.third = C(p.gi_correct ? 3.0 / g - 1.0 / (g * g) : 2.0);
-  k.A = C(4.0 / (g * g) - 1.0 / g);
-  k.B = C(1.0 / (g * g) - 1.0 / g);
-  k.Cg = C(1.0 / g - 1.0);
-  k.h3 = C(1.0 / p.omega3 - 0.5);
-  k.h4 = C(1.0 / w4 - 0.5);
-  k.h5 = C(1.0 / w4 - 0.5);
-  k.a3 = C(2.0 / (3.0 * p.omega3));
-  k.a4 = C(2.0 / (3.0 * w4));
-  k.w3 = C(p.omega3);
-  k.w4 = C(w4);
-  k.w5 = C(w4);
-  k.w6 = C(p.omega6);
-  k.w7 = C(p.omega7);
-  k.w8 = C(p.omega8);
-  k.fx = C(p.fx);
-  k.fy = C(p.fy);
-  k.u_lid = C(p.u_lid);
-  k.u_in_max = C(p.u_in_max);
-  k.scale = C(scale);
-  k.inv_scale = C(1.0 / scale);
-  k.gi = p.gi_correct ? 1 : 0;
-  k.force = (p.fx != 0.0 || p.fy != 0.0) ? 1 : 0;
-  k.stencil = p.drho_stencil;
-  return k;
-}
 
-// Framed, line-aligned layout: column 0 of every row starts a 128-byte line;
-// one ghost column/row on each side.
-Geom make_geom_for(int nx, int ny, const int32_t side[4], size_t esize) {
-  Geom g{};
-  g.nx = nx;
-  g.ny = ny;
-  for (int s = 0; s < 4; ++s) g.side[s] = side[s];
-  const int line = int(128 / esize);  // elements per 128-byte line
-  g.padx = line;
-  g.pitch = ((nx + 2 * line) + line - 1) / line * line;
-  g.plane = g.pitch * (ny + 2);
-  return g;
-}
 
 Geom make_geom(const lbm_ctx* c) { return make_geom_for(c->grid.nx, c->grid.ny, c->grid.side, c->esize); }
 
-int validate(const lbm_grid* grid, const uint8_t* solid, const lbm_params* p) {
-  if (!grid || !p) return fail(LBM_EINVAL, "null grid or params");
-  if (grid->nx < 2 || grid->ny < 2) return fail(LBM_EINVAL, "nx and ny must be >= 2");
-  {
-    const long long pitch = grid->nx + 2 * 64 + 64;
-    if (9LL * pitch * (grid->ny + 2) >= (1LL << 31))
-      return fail(LBM_EINVAL, "lattice too large (9 framed planes must hold fewer than 2^31 "
-                              "elements)");
-  }
-  for (int s = 0; s < 4; ++s)
-    if (grid->side[s] < LBM_SIDE_PERIODIC || grid->side[s] > LBM_SIDE_OUTLET)
-      return fail(LBM_EINVAL, "unknown side kind");
-  if ((grid->side[0] == LBM_SIDE_PERIODIC) != (grid->side[1] == LBM_SIDE_PERIODIC) ||
-      (grid->side[2] == LBM_SIDE_PERIODIC) != (grid->side[3] == LBM_SIDE_PERIODIC))
-    return fail(LBM_EINVAL, "a periodic side must face a periodic side");
-  for (int s = 0; s < 4; ++s) {
-    if (grid->side[s] == LBM_SIDE_INLET && s != 0) return fail(LBM_EINVAL, "INLET only on W");
-    if (grid->side[s] == LBM_SIDE_OUTLET && s != 1) return fail(LBM_EINVAL, "OUTLET only on E");
-  }
-  if (!(p->gamma > 0.0) || !(p->gamma <= 1.0)) return fail(LBM_EINVAL, "gamma must be in (0, 1]");
-  if (!(p->nu > 0.0)) return fail(LBM_EINVAL, "nu must be > 0");
-  if (p->storage < LBM_STORE_F64 || p->storage > LBM_STORE_F16)
-    return fail(LBM_EINVAL, "unknown storage");
-  if (p->check_every < 1) return fail(LBM_EINVAL, "check_every must be >= 1");
-  if (!(p->omega3 >= 0 && p->omega3 < 2) || !(p->omega6 >= 0 && p->omega6 < 2) ||
-      !(p->omega7 >= 0 && p->omega7 < 2) || !(p->omega8 >= 0 && p->omega8 < 2))
-    return fail(LBM_EINVAL, "omega3/6/7/8 must be in (0, 2) (0 selects 1.0)");
-  if (grid->side[1] == LBM_SIDE_OUTLET && solid) {
-    for (int j = 0; j < grid->ny; ++j)
-      if (solid[(size_t)j * grid->nx + grid->nx - 1] || solid[(size_t)j * grid->nx + grid->nx - 2])
-        return fail(LBM_EINVAL, "solid nodes next to an OUTLET side");
-  }
-  return LBM_OK;
-}
 
 int configure_tiles(lbm_ctx* c) {
   c->out_rows = c->by * c->rows;
@@ -352,7 +135,7 @@ void enqueue_step(lbm_ctx* c, hipStream_t st) {
     default: launch_step_f16(c->by, c->rows, flavor, src, dst, a, c->kf, st); break;
   }
   if (flavor == kCheck) {
-    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, st, c->partials, c->ntiles,
+    hipLaunchKernelGGL(finalize_kernel<256>, dim3(1), dim3(256), 0, st, c->partials, c->ntiles,
                        c->result);
     c->checked = true;
   }
@@ -455,7 +238,7 @@ void free_ctx(lbm_ctx* c) {
 
 extern "C" {
 
-const char* lbm_last_error(void) { return g_err.c_str(); }
+const char* lbm_last_error(void) { return lbmh::g_err.c_str(); }
 
 int lbm_launch_shapes(int32_t* shapes, int32_t cap) {
   for (int i = 0; i < kNumShapes && i < cap; ++i) {

@@ -1,0 +1,144 @@
+// Auxiliary kernels shared by the single-lattice API and the batch API:
+// fixed-order sum of block partials, equilibrium initialisation, boundary-
+// slot fill and export of populations / fields.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lbm_device.h"
+
+namespace lbmk {
+
+// Fixed-order sum of the per-tile partials: out[0..3].
+template <int kThreads = 256>
+__global__ __launch_bounds__(kThreads) void finalize_kernel(const double* __restrict__ partials,
+                                                       int n, double* __restrict__ out) {
+  __shared__ double s[4][256];
+  const int t = threadIdx.x;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = t; i < n; i += 256)
+    for (int c = 0; c < 4; ++c) a[c] += partials[(long long)i * 4 + c];
+  for (int c = 0; c < 4; ++c) s[c][t] = a[c];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h)
+      for (int c = 0; c < 4; ++c) s[c][t] += s[c][t + h];
+    __syncthreads();
+  }
+  if (t < 4) out[t] = s[t][0];
+}
+
+// Equilibrium initialisation from optional device fields; also writes the
+// velocity buffer and the outlet history.  Interior nodes of both lattices.
+template <class S, class FT>
+__global__ __launch_bounds__(256) void init_kernel(typename S::T* __restrict__ fa,
+                                                   typename S::T* __restrict__ fb, Geom g,
+                                                   Consts<typename S::C> k,
+                                                   const uint8_t* __restrict__ solid,
+                                                   const FT* __restrict__ rho,
+                                                   const FT* __restrict__ ux,
+                                                   const FT* __restrict__ uy,
+                                                   typename S::C* __restrict__ ubuf,
+                                                   typename S::C* __restrict__ hist0,
+                                                   typename S::C* __restrict__ hist1) {
+  using C = typename S::C;
+  const long long np = (long long)g.nx * g.ny;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  const bool sol = solid && solid[i];
+  C drho = C(0), vx = C(0), vy = C(0);
+  if (!sol) {
+    if (rho) drho = C(rho[i]) - k.rho0;
+    if (ux) vx = C(ux[i]);
+    if (uy) vy = C(uy[i]);
+  }
+  C f[9];
+  equilibrium_dev<C>(drho, vx, vy, k, f);
+  const int x = int(i % g.nx), y = int(i / g.nx);
+  const long long li = gidx(g, x, y);
+#pragma unroll
+  for (int a = 0; a < 9; ++a) {
+    const typename S::T v = S::enc(f[a], k.scale);
+    fa[(long long)a * g.plane + li] = v;
+    fb[(long long)a * g.plane + li] = v;
+  }
+  ubuf[i] = vx;
+  ubuf[np + i] = vy;
+  if (x == g.nx - 1) {
+    hist0[y] = vx;
+    hist0[g.ny + y] = vy;
+    hist1[y] = vx;
+    hist1[g.ny + y] = vy;
+  }
+}
+
+// Boundary slots of a lattice from its own fluid-node values (after an
+// initialisation or a checkpoint load).
+template <class S>
+__global__ __launch_bounds__(256) void ghost_fill_kernel(typename S::T* __restrict__ fa, Geom g,
+                                                         Consts<typename S::C> k,
+                                                         const uint8_t* __restrict__ solid) {
+  using C = typename S::C;
+  const long long np = (long long)g.nx * g.ny;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  if (solid && solid[i]) return;
+  const int x = int(i % g.nx), y = int(i / g.nx);
+  C d[9];
+  const long long li = gidx(g, x, y);
+#pragma unroll
+  for (int a = 0; a < 9; ++a) d[a] = S::dec(fa[a * g.plane + li], k.inv_scale);
+  auto nonfluid = [&](int a) {
+    int gx, gy;
+    return !region_node(g, solid, x - ex_of(a), y - ey_of(a), gx, gy);
+  };
+  ghost_writes<S>(fa, g, k, x, y, d, nonfluid);
+}
+
+// Decode populations (full f) or macroscopic fields of the current lattice.
+template <class S>
+__global__ __launch_bounds__(256) void export_kernel(const typename S::T* __restrict__ fa, Geom g,
+                                                     Consts<typename S::C> k,
+                                                     const uint8_t* __restrict__ solid,
+                                                     double* __restrict__ pops,
+                                                     float* __restrict__ rho_o,
+                                                     float* __restrict__ ux_o,
+                                                     float* __restrict__ uy_o,
+                                                     double* __restrict__ rho_d,
+                                                     double* __restrict__ ux_d,
+                                                     double* __restrict__ uy_d) {
+  using C = typename S::C;
+  const long long np = (long long)g.nx * g.ny;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  const long long li = gidx(g, int(i % g.nx), int(i / g.nx));
+  C d[9];
+#pragma unroll
+  for (int a = 0; a < 9; ++a) d[a] = S::dec(fa[a * g.plane + li], k.inv_scale);
+  if (pops) {
+#pragma unroll
+    for (int a = 0; a < 9; ++a)
+      pops[a * np + i] = double(d[a]) + double(w_of<C>(a)) * double(k.rho0);
+  }
+  const bool sol = solid && solid[i];
+  // post-collision moments: rho is unchanged by collision; the momentum has
+  // received F/gamma, so u = (sum e f~ - F/(2 gamma)) / rho
+  C drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
+  C jx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
+  C jy = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
+  if (k.force) {
+    jx -= C(0.5) * k.fx * k.ig;
+    jy -= C(0.5) * k.fy * k.ig;
+  }
+  const C rho = k.rho0 + drho;
+  const C vx = jx / rho, vy = jy / rho;
+  if (rho_o) rho_o[i] = sol ? 0.f : float(rho);
+  if (ux_o) ux_o[i] = sol ? 0.f : float(vx);
+  if (uy_o) uy_o[i] = sol ? 0.f : float(vy);
+  if (rho_d) rho_d[i] = sol ? 0.0 : double(k.rho0) + double(drho);
+  if (ux_d) ux_d[i] = sol ? 0.0 : double(vx);
+  if (uy_d) uy_d[i] = sol ? 0.0 : double(vy);
+}
+
+
+}  // namespace lbmk

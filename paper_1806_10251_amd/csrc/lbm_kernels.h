@@ -120,22 +120,23 @@ __device__ __forceinline__ void block_partials(double acc[4], double (*s_red)[4]
   }
 }
 
+// One tile of the fused step (the body of both the single-lattice kernel and
+// the persistent batch kernel).  LDS: s_rho[(BY*R + 2) * 66] of type C,
+// s_red[BY * 4].
 template <class S, int BY, int R, int FL, bool OBST, bool OUTL>
-__global__ __launch_bounds__(kLanes* BY) void step_kernel(const typename S::T* __restrict__ fa,
-                                                          typename S::T* __restrict__ fb,
-                                                          const StepArgs args,
-                                                          const Consts<typename S::C> k) {
+__device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
+                                          typename S::T* __restrict__ fb, const StepArgs& args,
+                                          const Consts<typename S::C>& k, int tile,
+                                          typename S::C (*s_rho)[kLanes + 2],
+                                          double (*s_red)[4]) {
   using C = typename S::C;
   constexpr int RO = BY * R;   // output rows of the tile
   constexpr int RR = RO + 2;   // region rows (one halo row above and below)
   constexpr int W = kLanes + 2;
   const C SENT = C(HUGE_VALF);
-  __shared__ C s_rho[RR][W];
-  __shared__ double s_red[BY][4];
   const Geom& g = args.g;
   const int lane = threadIdx.x;
   const int w = threadIdx.y;
-  const int tile = xcd_tile(blockIdx.x, args.ntiles);
   const int tx = tile % args.tiles_x;
   const int ty = tile / args.tiles_x;
   const int x = tx * kLanes + lane;
@@ -257,6 +258,18 @@ __global__ __launch_bounds__(kLanes* BY) void step_kernel(const typename S::T* _
     }
   }
   if (FL == kCheck) block_partials<BY>(acc, s_red, lane, w, args.partials + (long long)tile * 4);
+}
+
+template <class S, int BY, int R, int FL, bool OBST, bool OUTL>
+__global__ __launch_bounds__(kLanes* BY) void step_kernel(const typename S::T* __restrict__ fa,
+                                                          typename S::T* __restrict__ fb,
+                                                          const StepArgs args,
+                                                          const Consts<typename S::C> k) {
+  using C = typename S::C;
+  __shared__ C s_rho[BY * R + 2][kLanes + 2];
+  __shared__ double s_red[BY][4];
+  step_tile<S, BY, R, FL, OBST, OUTL>(fa, fb, args, k, xcd_tile(blockIdx.x, args.ntiles), s_rho,
+                                      s_red);
 }
 
 // One fused step over all tiles (one block per tile).

@@ -312,9 +312,13 @@ class Batch:
         _check(load().lbm_batch_set_launch(self._h, int(rows_per_item), int(blocks)))
 
     def run(self, tol, max_steps):
+        """Run until every case's residual < tol (checked every check_every
+        steps) or max_steps.  Returns the steps each case took; a case that
+        diverged has its step count negated (and self.diverged is set)."""
         steps = np.zeros(self.n, dtype=np.int64)
         rc = load().lbm_batch_run(self._h, float(tol), int(max_steps),
                                   steps.ctypes.data_as(ctypes.c_void_p))
+        self.diverged = rc == LBM_EUNSTABLE
         if rc not in (LBM_OK, LBM_EUNSTABLE):
             _check(rc)
         return steps
