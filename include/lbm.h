@@ -142,6 +142,11 @@ int lbm_populations(lbm_ctx* ctx, double* f);
 int lbm_save(lbm_ctx* ctx, const char* path);
 int lbm_load(lbm_ctx* ctx, const char* path);
 
+/* Convert the current state to another storage type in place (used to
+ * finish a run in FP64 once FP32 storage has reached its rounding floor).
+ * storage_scale as in lbm_params.  Rebuilds cached graphs. */
+int lbm_set_storage(lbm_ctx* ctx, int32_t storage, double storage_scale);
+
 /* Launch shape of the fused step: block of 64 x by threads, each thread
  * holding `rows` lattice rows (the autotuner's knobs).  Supported pairs are
  * listed by lbm_launch_shapes.  Rebuilds cached graphs. */
@@ -162,13 +167,15 @@ void lbm_destroy(lbm_ctx* ctx);
 const char* lbm_last_error(void);
 
 /* ---------------------------------------------------------------------- */
-/* Batch: n independent steady cases advanced together by one persistent  */
-/* kernel (a grid-wide barrier per time step; a case retires when its     */
-/* residual falls below tol at a check step).  Storage is FP32 deviations. */
+/* Batch: n independent steady cases advanced together, each time step    */
+/* one launch over the tiles of every active case (a case retires when    */
+/* its residual falls below tol at a check step, or stops improving).     */
+/* Storage is FP32 or FP64 deviations for all cases.                      */
 /* ---------------------------------------------------------------------- */
 
 /* grids[c], masks[c] (ny*nx bytes or NULL), params[c] for c < n.  All
- * params must use LBM_STORE_F32 and the same check_every.  Inputs copied. */
+ * params must use the same storage (LBM_STORE_F32 or LBM_STORE_F64) and the
+ * same check_every.  Inputs copied. */
 int lbm_batch_create(int32_t n, const lbm_grid* grids, const uint8_t* const* masks,
                      const lbm_params* params, lbm_batch** out);
 
@@ -187,13 +194,36 @@ int lbm_batch_set_stream(lbm_batch* b, void* hip_stream);
  * diverged (that case retires with its step count negated). */
 int lbm_batch_run(lbm_batch* b, double tol, int64_t max_steps, int64_t* steps_per_case);
 
+/* Plateau retirement: a case also retires (status 2) once its residual has
+ * not dropped below factor * (its best residual) for `checks` consecutive
+ * check steps (checks = 0 disables; default).  This is how an FP32 run
+ * detects its rounding floor. */
+int lbm_batch_set_plateau(lbm_batch* b, int32_t checks, double factor);
+
+/* Per-case outcome of the last lbm_batch_run (n entries): 0 still running at
+ * max_steps, 1 converged (residual < tol), 2 plateau, 3 diverged. */
+int lbm_batch_status(lbm_batch* b, int32_t* status);
+
+/* Which cases the next runs advance (n entries, nonzero = advance; NULL =
+ * all).  Disabled cases keep their state. */
+int lbm_batch_set_enabled(lbm_batch* b, const int32_t* enabled);
+
+/* Convert every case's state to LBM_STORE_F32 or LBM_STORE_F64 in place. */
+int lbm_batch_set_storage(lbm_batch* b, int32_t storage);
+
 /* Residual of case c at its last check step. */
 int lbm_batch_residual(lbm_batch* b, int32_t c, double* r);
 
 int lbm_batch_fields(lbm_batch* b, int32_t c, double* rho, double* ux, double* uy);
 
-/* Tile rows per work item and persistent grid size (0 = automatic). */
-int lbm_batch_set_launch(lbm_batch* b, int32_t rows_per_item, int32_t blocks);
+/* Launch knobs of the batch (the autotuner's).  rows_per_item: block height
+ * in wavefronts of one lattice row each, 4, 8 or 16 (0 = 4).  schedule:
+ * 0 = one step kernel per time step over all active tiles, case after case,
+ * a window of check_every steps captured into a HIP graph and replayed;
+ * 1 = the same with tiles interleaved across cases; 2 = one persistent
+ * kernel per window in which each tile waits only for its own case's
+ * previous step (per-case counters).  LBM_EINVAL for other values. */
+int lbm_batch_set_launch(lbm_batch* b, int32_t rows_per_item, int32_t schedule);
 
 void lbm_batch_destroy(lbm_batch* b);
 

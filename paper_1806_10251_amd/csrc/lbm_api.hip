@@ -579,6 +579,75 @@ int lbm_load(lbm_ctx* c, const char* path) {
   return LBM_OK;
 }
 
+
+int lbm_set_storage(lbm_ctx* c, int32_t storage, double storage_scale) {
+  if (!c) return fail(LBM_EINVAL, "null context");
+  if (storage < LBM_STORE_F64 || storage > LBM_STORE_F16) return fail(LBM_EINVAL, "unknown storage");
+  double scale = 1.0;
+  if (storage == LBM_STORE_BF16 || storage == LBM_STORE_F16) {
+    scale = storage_scale > 0 ? storage_scale : (storage == LBM_STORE_F16 ? 4096.0 : 1.0);
+    int e;
+    if (std::frexp(scale, &e) != 0.5) return fail(LBM_EINVAL, "storage_scale must be a power of two");
+  }
+  HIPCHECK(hipStreamSynchronize(c->stream));
+  const Geom g1 = make_geom(c);
+  const int s1 = c->p.storage;
+  const double inv1 = s1 == LBM_STORE_F64 ? double(c->kd.inv_scale) : double(c->kf.inv_scale);
+  const size_t esize2 = storage_bytes(storage), csize2 = storage == LBM_STORE_F64 ? 8 : 4;
+  const Geom g2 = make_geom_for(c->grid.nx, c->grid.ny, c->grid.side, esize2);
+  const size_t np = (size_t)c->grid.nx * c->grid.ny;
+  void* lat2[2] = {nullptr, nullptr};
+  void* hist2[2] = {nullptr, nullptr};
+  void* ubuf2 = nullptr;
+  bool ok = true;
+  for (int i = 0; ok && i < 2; ++i)
+    ok = hipMalloc(&lat2[i], 9 * (size_t)g2.plane * esize2) == hipSuccess &&
+         hipMemset(lat2[i], 0, 9 * (size_t)g2.plane * esize2) == hipSuccess &&
+         hipMalloc(&hist2[i], 2 * (size_t)c->grid.ny * csize2) == hipSuccess;
+  ok = ok && hipMalloc(&ubuf2, 2 * np * csize2) == hipSuccess;
+  if (!ok) {
+    for (int i = 0; i < 2; ++i) {
+      hipFree(lat2[i]);
+      hipFree(hist2[i]);
+    }
+    hipFree(ubuf2);
+    return fail(LBM_ENOMEM, "allocation for the new storage failed");
+  }
+  const long long nf = (long long)(c->grid.nx + 2) * (c->grid.ny + 2);
+  for (int i = 0; i < 2; ++i) {
+    hipLaunchKernelGGL(convert_lattice_kernel, dim3(int((nf + 255) / 256)), dim3(256), 0, c->stream,
+                       c->lat[i], s1, g1, inv1, lat2[i], (int)storage, g2, scale);
+    const long long nh = 2LL * c->grid.ny;
+    hipLaunchKernelGGL(convert_values_kernel, dim3(int((nh + 255) / 256)), dim3(256), 0, c->stream,
+                       c->hist[i], int(c->csize == 8), hist2[i], int(csize2 == 8), nh);
+  }
+  hipLaunchKernelGGL(convert_values_kernel, dim3(int((2 * np + 255) / 256)), dim3(256), 0,
+                     c->stream, c->ubuf, int(c->csize == 8), ubuf2, int(csize2 == 8),
+                     (long long)(2 * np));
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipStreamSynchronize(c->stream));
+  for (int i = 0; i < 2; ++i) {
+    hipFree(c->lat[i]);
+    hipFree(c->hist[i]);
+    c->lat[i] = lat2[i];
+    c->hist[i] = hist2[i];
+  }
+  hipFree(c->ubuf);
+  c->ubuf = ubuf2;
+  c->p.storage = storage;
+  c->p.storage_scale = storage_scale;
+  c->esize = esize2;
+  c->csize = csize2;
+  c->kd = make_consts<double>(c->p, scale);
+  c->kf = make_consts<float>(c->p, scale);
+  for (int i = 0; i < 2; ++i)
+    if (c->graph[i]) {
+      hipGraphExecDestroy(c->graph[i]);
+      c->graph[i] = nullptr;
+    }
+  return LBM_OK;
+}
+
 int lbm_set_launch(lbm_ctx* c, int32_t by, int32_t rows) {
   if (!c) return fail(LBM_EINVAL, "null context");
   bool known = false;

@@ -141,4 +141,51 @@ __global__ __launch_bounds__(256) void export_kernel(const typename S::T* __rest
 }
 
 
+// Storage conversion of one framed lattice (interior and ghost frame), from
+// storage s1 to storage s2 (LBM_STORE_* codes), through FP64.  The two
+// layouts may differ in row padding.
+__device__ __forceinline__ double load_any(const void* p, int storage, long long i, double inv) {
+  switch (storage) {
+    case 0: return static_cast<const double*>(p)[i];
+    case 1: return double(static_cast<const float*>(p)[i]);
+    case 2: return double(StoreBF16::dec(static_cast<const uint16_t*>(p)[i], float(inv)));
+    default: return double(StoreF16::dec(static_cast<const _Float16*>(p)[i], float(inv)));
+  }
+}
+__device__ __forceinline__ void store_any(void* p, int storage, long long i, double v,
+                                          double scale) {
+  switch (storage) {
+    case 0: static_cast<double*>(p)[i] = v; break;
+    case 1: static_cast<float*>(p)[i] = float(v); break;
+    case 2: static_cast<uint16_t*>(p)[i] = StoreBF16::enc(float(v), float(scale)); break;
+    default: static_cast<_Float16*>(p)[i] = StoreF16::enc(float(v), float(scale)); break;
+  }
+}
+
+__global__ __launch_bounds__(256) inline void convert_lattice_kernel(
+    const void* __restrict__ src, int s1, Geom g1, double inv1, void* __restrict__ dst, int s2,
+    Geom g2, double sc2) {
+  const long long nfx = (long long)(g1.nx + 2), nfy = (long long)(g1.ny + 2);
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nfx * nfy) return;
+  const int x = int(i % nfx) - 1, y = int(i / nfx) - 1;
+  const long long i1 = gidx(g1, x, y), i2 = gidx(g2, x, y);
+  for (int a = 0; a < 9; ++a)
+    store_any(dst, s2, (long long)a * g2.plane + i2,
+              load_any(src, s1, (long long)a * g1.plane + i1, inv1), sc2);
+}
+
+// float <-> double copy of small state arrays (velocity buffer, history)
+__global__ __launch_bounds__(256) inline void convert_values_kernel(const void* __restrict__ src,
+                                                                    int src_double,
+                                                                    void* __restrict__ dst,
+                                                                    int dst_double, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = src_double ? static_cast<const double*>(src)[i]
+                              : double(static_cast<const float*>(src)[i]);
+  if (dst_double) static_cast<double*>(dst)[i] = v;
+  else static_cast<float*>(dst)[i] = float(v);
+}
+
 }  // namespace lbmk

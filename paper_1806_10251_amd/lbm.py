@@ -29,6 +29,8 @@ EXPORTS = (
     "lbm_last_error", "lbm_batch_create", "lbm_batch_init_fields",
     "lbm_batch_init_fields_device", "lbm_batch_set_stream", "lbm_batch_run",
     "lbm_batch_residual", "lbm_batch_fields", "lbm_batch_set_launch", "lbm_batch_destroy",
+    "lbm_set_storage", "lbm_batch_set_plateau", "lbm_batch_status", "lbm_batch_set_enabled",
+    "lbm_batch_set_storage",
 )
 
 
@@ -98,6 +100,11 @@ def load():
         "lbm_batch_residual": [vp, i32, P(dbl)],
         "lbm_batch_fields": [vp, i32, vp, vp, vp],
         "lbm_batch_set_launch": [vp, i32, i32],
+        "lbm_set_storage": [vp, i32, dbl],
+        "lbm_batch_set_plateau": [vp, i32, dbl],
+        "lbm_batch_status": [vp, vp],
+        "lbm_batch_set_enabled": [vp, vp],
+        "lbm_batch_set_storage": [vp, i32],
     }
     for name, args in sig.items():
         if not hasattr(L, name):
@@ -244,6 +251,10 @@ class Lattice:
         _check(load().lbm_populations(self._h, f.ctypes.data_as(ctypes.c_void_p)))
         return f
 
+    def set_storage(self, storage, storage_scale=0.0):
+        st = STORAGE_NAMES[storage] if isinstance(storage, str) else int(storage)
+        _check(load().lbm_set_storage(self._h, st, float(storage_scale)))
+
     def save(self, path):
         _check(load().lbm_save(self._h, str(path).encode()))
 
@@ -308,8 +319,11 @@ class Batch:
         raw = getattr(stream, "cuda_stream", stream)
         _check(load().lbm_batch_set_stream(self._h, ctypes.c_void_p(raw) if raw else None))
 
-    def set_launch(self, rows_per_item=0, blocks=0):
-        _check(load().lbm_batch_set_launch(self._h, int(rows_per_item), int(blocks)))
+    def set_launch(self, rows_per_item=0, schedule=0):
+        """rows_per_item: block height 4, 8 or 16 (0 = 4); schedule 0 graph
+        of per-step kernels case after case, 1 tiles interleaved across
+        cases, 2 persistent dataflow kernel."""
+        _check(load().lbm_batch_set_launch(self._h, int(rows_per_item), int(schedule)))
 
     def run(self, tol, max_steps):
         """Run until every case's residual < tol (checked every check_every
@@ -327,6 +341,25 @@ class Batch:
         r = ctypes.c_double()
         _check(load().lbm_batch_residual(self._h, int(c), ctypes.byref(r)))
         return r.value
+
+    def set_plateau(self, checks, factor=0.9):
+        _check(load().lbm_batch_set_plateau(self._h, int(checks), float(factor)))
+
+    def status(self):
+        st = np.zeros(self.n, dtype=np.int32)
+        _check(load().lbm_batch_status(self._h, st.ctypes.data_as(ctypes.c_void_p)))
+        return st
+
+    def set_enabled(self, enabled=None):
+        if enabled is None:
+            _check(load().lbm_batch_set_enabled(self._h, None))
+        else:
+            e = np.ascontiguousarray(enabled, dtype=np.int32)
+            _check(load().lbm_batch_set_enabled(self._h, e.ctypes.data_as(ctypes.c_void_p)))
+
+    def set_storage(self, storage):
+        st = STORAGE_NAMES[storage] if isinstance(storage, str) else int(storage)
+        _check(load().lbm_batch_set_storage(self._h, st))
 
     def fields(self, c, ny, nx):
         out = [np.zeros((ny, nx)) for _ in range(3)]

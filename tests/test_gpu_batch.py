@@ -51,14 +51,14 @@ def make_batch(L, cases, K=100):
     return L.Batch(grids, masks, params)
 
 
-@pytest.mark.parametrize("by", [4, 8, 16])
-def test_batch_matches_single_lattice_runs(lbm, by):
+@pytest.mark.parametrize("by,sched", [(4, 0), (8, 0), (16, 0), (4, 2)])
+def test_batch_matches_single_lattice_runs(lbm, by, sched):
     """Each case retired by the batch equals a single-lattice run of the same
     number of steps (same arithmetic, bit for bit up to rounding order)."""
     cases = small_cases()
-    _say("batch vs single, block height", by)
+    _say("batch vs single, block height", by, "schedule", sched)
     b = make_batch(lbm, cases)
-    b.set_launch(by, 0)
+    b.set_launch(by, sched)
     steps = b.run(1e-6, 30000)
     _say("steps per case", list(steps))
     assert all(s > 0 for s in steps)
@@ -77,17 +77,34 @@ def test_batch_matches_single_lattice_runs(lbm, by):
     b.close()
 
 
-def test_batch_round_robin_schedule(lbm):
+@pytest.mark.parametrize("sched,chunks", [(1, (300,)), (2, (300,)), (0, (130, 70, 100)),
+                                          (2, (1, 149, 150))])
+def test_batch_schedules_and_partial_windows(lbm, sched, chunks):
+    """Interleaved and dataflow schedules, and runs that stop between check
+    steps (partial windows), give the single-lattice result."""
     cases = small_cases()[:3]
+    _say("schedule", sched, "chunks", chunks)
     b = make_batch(lbm, cases)
-    b.set_launch(4, -64)      # 64 blocks, round-robin items
-    steps = b.run(0.0, 300)
-    assert all(s == 300 for s in steps)
+    b.set_launch(4, sched)
+    total = np.zeros(len(cases), dtype=np.int64)
+    for n in chunks:
+        total += b.run(0.0, n)
+    assert all(s == 300 for s in total)
     for i, c in enumerate(cases):
         g = lbm.Lattice(c["nx"], c["ny"], c["sides"], solid=c["solid"], storage="f32",
                         check_every=100, **c["kw"])
         g.step(300)
         np.testing.assert_allclose(b.fields(i, c["ny"], c["nx"])[1], g.fields()[1], atol=1e-7)
+        g.close()
+    b.close()
+
+
+def test_batch_rejects_bad_launch(lbm):
+    b = make_batch(lbm, small_cases()[:1])
+    with pytest.raises(lbm.LbmError):
+        b.set_launch(5, 0)
+    with pytest.raises(lbm.LbmError):
+        b.set_launch(4, 3)
 
 
 def test_batch_against_oracle(lbm):

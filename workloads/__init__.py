@@ -116,7 +116,9 @@ def random_obstacles(rng: SplitMix64, nx: int, ny: int, kind: str,
 
     Rectangles keep a margin of 2 nodes from every side (3 from the lid row
     of a cavity, and 4 from the inlet/outlet columns of a channel) and are
-    redrawn when the fluid would be split into disconnected parts.
+    redrawn when the fluid would be split into disconnected parts, or when a
+    channel cross-section would be more than half blocked (a velocity inlet
+    then needs a pressure rise the weakly compressible scheme cannot hold).
     """
     area = nx * ny
     for _ in range(max_tries):
@@ -146,6 +148,10 @@ def random_obstacles(rng: SplitMix64, nx: int, ny: int, kind: str,
             continue
         cover = m.sum() / area
         if cover < cover_lo or cover > cover_hi:
+            continue
+        if kind == "channel" and m.sum(axis=0).max() > ny // 2:
+            continue      # keep at least half of every cross-section open
+        if kind == "cavity" and (m.sum(axis=0).max() > ny - 6 or m.sum(axis=1).max() > nx - 6):
             continue
         if not _fluid_connected(m):
             continue
