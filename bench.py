@@ -8,6 +8,11 @@ links, macroscopic fields, density gradient, strain estimate, GI
 corrections, cascaded collision; FP64 residual/mass on check steps) over the
 lattice, with the populations resident in HBM.
 
+Second leg (time_to_steady): a seeded sample of the batched workload (mixed
+cavities and channels with obstacles, uneven sizes, Re and gamma), every case
+run to residual < 1e-8 in FP64 storage, once case after case with the plain
+single-lattice driver and once as one batch; wall times of both.
+
 Prints one JSON line (rank 0).  --gpus above 1 is not supported: the method
 runs on one GPU here (see the design notes for how it would shard).
 """
@@ -47,6 +52,88 @@ def cpu_baseline(n, U, re, gamma, budget_s=12.0):
                       f"steps, FP64, {el:.1f} s"}
 
 
+# Kernel sources whose HBM byte counters the committed traffic summary holds;
+# the figure is reported only while their hash matches.
+TRAFFIC_SOURCES = ("paper_1806_10251_amd/csrc/lbm_kernels.h",
+                   "paper_1806_10251_amd/csrc/lbm_device.h",
+                   "paper_1806_10251_amd/csrc/lbm_step_f32.hip")
+TRAFFIC_SUMMARY = "profiles/step_f32_cavity1024_hbm_traffic.md"
+
+
+def source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(storage, n, by, rows):
+    """HBM bytes per step launch from the committed counter summary, if it
+    was taken for this kernel source, storage, size and launch shape."""
+    try:
+        with open(os.path.join(ROOT, TRAFFIC_SUMMARY)) as f:
+            kv = dict(line[2:].split(": ", 1) for line in f if line.startswith("- ") and ": " in line)
+    except OSError:
+        return None
+    want = {"source_hash": source_hash(), "storage": storage, "size": f"{n}x{n}",
+            "launch": f"{by},{rows}"}
+    if any(kv.get(k, "").strip() != v for k, v in want.items()):
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def _case_kw(k):
+    kw = {"u_lid": k.u_ref} if k.kind == "cavity" else {"u_in_max": k.u_ref}
+    return dict(nu=k.nu, gamma=k.gamma, **kw)
+
+
+def time_to_steady(lbm, n_cases, side_hi, max_steps, seed=1806, tol=1e-8):
+    """Plain (one case after another) versus batched time to steady state."""
+    import numpy as np
+    import torch
+
+    from paper_1806_10251_amd import autotune, steady
+    from workloads import draw_cases
+
+    cases = draw_cases(n_cases, seed, side_lo=64, side_hi=side_hi)
+    grids = [lbm.make_grid(k.nx, k.ny, k.sides) for k in cases]
+    masks = [k.mask for k in cases]
+    params = [lbm.make_params(storage="f64", check_every=100, **_case_kw(k)) for k in cases]
+    print(f"[bench] time-to-steady: {n_cases} cases, {sum(k.nx * k.ny for k in cases)} nodes; "
+          "tuning the batch", file=sys.stderr, flush=True)
+    choice, _ = autotune.tune_batch(grids, masks, params, steps=200)
+    b = lbm.Batch(grids, masks, params)
+    autotune.apply_batch_choice(b, choice)
+    torch.cuda.synchronize()
+    steps_b, st_b, t_batch = steady.run_batch(b, tol=tol, max_steps=max_steps)
+    b.close()
+    print(f"[bench] batch {t_batch:.2f} s; plain runs", file=sys.stderr, flush=True)
+    t_plain, same, status = 0.0, True, {}
+    names = {1: "converged", 3: "diverged", 0: "max_steps", 2: "plateau"}
+    for i, k in enumerate(cases):
+        lat = lbm.Lattice(k.nx, k.ny, k.sides, solid=k.mask, storage="f64", check_every=100,
+                          **_case_kw(k))
+        torch.cuda.synchronize()
+        r = steady.run_single(lat, tol=tol, max_steps=max_steps)
+        lat.close()
+        t_plain += r.seconds
+        same &= (r.steps == int(steps_b[i]) and r.status == names[int(st_b[i])])
+        status[r.status] = status.get(r.status, 0) + 1
+    return {"tol": tol, "storage": "f64", "cases": n_cases,
+            "sample": f"seeded mix (seed {seed}) of cavities s x s and channels 4s x s, s in "
+                      f"[64, {side_hi}], 1-4 rectangular obstacles covering 5-20%, Re in "
+                      f"[50, 1000], gamma log-uniform in [0.05, 1]; at most {max_steps} steps",
+            "plain_s": round(t_plain, 3), "batch_s": round(t_batch, 3),
+            "speedup": round(t_plain / t_batch, 3), "status": status,
+            "batch_launch": {"block_height": choice[0], "schedule": choice[1]},
+            "same_steps_and_outcome": bool(same), "warm_start": None}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -57,6 +144,12 @@ def main():
     ap.add_argument("--storage", default="f32", choices=list(BYTES_PER_LUP))
     ap.add_argument("--launch", default="", help="by,rows (default: library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tts-cases", type=int, default=24)
+    ap.add_argument("--tts-side", type=int, default=128)
+    ap.add_argument("--tts-max-steps", type=int, default=200000)
+    ap.add_argument("--no-tts", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run a 256 MiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -75,6 +168,14 @@ def main():
     torch.cuda.set_device(0)
     lbm.load()
 
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     n, U, re, gamma = args.n, 0.1, 1000.0, args.gamma
     K = 100
     print(f"[bench] cavity {n}x{n} Re {re:g} gamma {gamma:g} {args.storage}; "
@@ -83,7 +184,12 @@ def main():
                       u_lid=U, check_every=K)
     if args.launch:
         by, rows = (int(v) for v in args.launch.split(","))
-        lat.set_launch(by, rows)
+    else:
+        from paper_1806_10251_amd import autotune
+        (by, rows), _ = autotune.tune_lattice(n, n, cavity_sides(), storage=args.storage,
+                                              use_cache=False, nu=U * n / re, gamma=gamma,
+                                              u_lid=U)
+    lat.set_launch(by, rows)
     stream = torch.cuda.current_stream()
     lat.set_stream(stream)
     lat.step(args.warmup)
@@ -102,7 +208,6 @@ def main():
     mlups = lups / wall / 1e6
     bpl = BYTES_PER_LUP[args.storage]
     achieved = bpl * n * n / (step_ms_dev * 1e-3) / 1e9
-    by, rows = lat.get_launch()
     out = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -122,13 +227,16 @@ def main():
                    "launch": {"block": [64, by], "rows_per_thread": rows}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "traffic": None,
+                     "traffic": measured_traffic(args.storage, n, by, rows),
                      "note": f"{bpl} B/LUP algorithmic (each population read and written once) x "
                              f"{n * n} nodes per launch / average step time "
                              f"{step_ms_dev * 1e3:.2f} us from HIP events"},
         "residual_at_end": resid,
         "mass_drift": mass - n * n,
     }
+    if not args.no_tts:
+        out["time_to_steady"] = time_to_steady(lbm, args.tts_cases, args.tts_side,
+                                               args.tts_max_steps)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(n, U, re, gamma)

@@ -471,11 +471,19 @@ orc *orc_create(int nx, int ny, const int32_t side[4], const uint8_t *solid,
     return NULL;
   }
   if (solid) memcpy(o->solid, solid, n);
+  {
+    size_t fluid = 0;
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) fluid += !is_solid(o, i, j);
+    if (fluid == 0) o->p.gamma = 0; /* no fluid node: invalid */
+  }
   if (sd[SE] == ORC_OUTLET) {
     for (int j = 0; j < ny; ++j)
       if (is_solid(o, nx - 1, j) || is_solid(o, nx - 2, j)) {
         o->p.gamma = 0; /* mark invalid */
       }
+  }
+  {
     if (o->p.gamma == 0) {
       free(o->solid); free(o->f); free(o->fb); free(o->rho); free(o->ux); free(o->uy);
       free(o->uxp); free(o->uyp); free(o->drx); free(o->dry); free(o->hist); free(o->hist_next); free(o);

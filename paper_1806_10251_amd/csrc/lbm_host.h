@@ -110,6 +110,12 @@ inline int validate(const lbm_grid* grid, const uint8_t* solid, const lbm_params
   if (!(p->omega3 >= 0 && p->omega3 < 2) || !(p->omega6 >= 0 && p->omega6 < 2) ||
       !(p->omega7 >= 0 && p->omega7 < 2) || !(p->omega8 >= 0 && p->omega8 < 2))
     return fail(LBM_EINVAL, "omega3/6/7/8 must be in (0, 2) (0 selects 1.0)");
+  if (solid) {
+    const size_t n = (size_t)grid->nx * grid->ny;
+    size_t fluid = 0;
+    for (size_t i = 0; i < n; ++i) fluid += solid[i] == 0;
+    if (fluid == 0) return fail(LBM_EINVAL, "the mask leaves no fluid node");
+  }
   if (grid->side[1] == LBM_SIDE_OUTLET && solid) {
     for (int j = 0; j < grid->ny; ++j)
       if (solid[(size_t)j * grid->nx + grid->nx - 1] || solid[(size_t)j * grid->nx + grid->nx - 2])

@@ -281,7 +281,7 @@ class Lattice:
 
 
 class Batch:
-    """Many independent lattices advanced by one persistent kernel."""
+    """Many independent lattices advanced together (schedules: set_launch)."""
 
     def __init__(self, cases_grids, masks, params_list):
         L = load()

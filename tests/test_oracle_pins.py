@@ -453,3 +453,5 @@ def test_rejects_invalid_configuration(oracle_lib):
     m[4, 7] = 1
     with pytest.raises(ValueError):
         oracle.Oracle(8, 8, channel_sides(), solid=m, nu=0.1, gamma=1.0)  # solid at outlet
+    with pytest.raises(ValueError):
+        oracle.Oracle(8, 8, cavity_sides(), solid=np.ones((8, 8), np.uint8), nu=0.1, gamma=1.0)

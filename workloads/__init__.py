@@ -176,8 +176,9 @@ class Case:
 
     @property
     def length(self):
-        """Reynolds length: wall-to-wall distance (cavity) or channel height."""
-        return self.nx if self.kind == "cavity" else self.ny
+        """Reynolds length: the long side of the domain (cavity side, channel
+        length)."""
+        return self.nx
 
     @property
     def nu(self):
@@ -185,13 +186,22 @@ class Case:
 
 
 def draw_cases(n: int, seed: int, side_lo=64, side_hi=512, re_lo=50.0, re_hi=1000.0,
-               gamma_lo=0.05, gamma_hi=1.0, u_ref=0.1, channel_frac=0.5,
-               u_over_gamma_max=None):
+               gamma_lo=0.05, gamma_hi=1.0, u_cavity=0.1, u_channel=0.05, channel_frac=0.5,
+               ma_cavity=0.3, ma_channel=0.1, gi_max=0.2):
     """Seeded mix of cavities (s x s) and channels (4s x s) with obstacles.
 
-    ``u_over_gamma_max``: when set, the reference speed of a case is lowered
-    to ``u_over_gamma_max * gamma`` if that is smaller than ``u_ref`` (the
-    deviation used for cases that are unstable as drawn).
+    Reference speeds: lid speed ``u_cavity`` and inlet peak ``u_channel``,
+    each lowered where needed so that
+      * the preconditioned Mach number U / sqrt(gamma / 3) stays at or below
+        ``ma_cavity`` / ``ma_channel`` (the channel bound is lower because
+        flow through the gaps between obstacles runs about three times
+        faster than the inlet peak), and
+      * the size of the third-order GI correction coefficients at the
+        fastest node, (1/omega - 1/2)(4/gamma^2 - 1/gamma) u_max^2 with
+        1/omega - 1/2 = 3 nu / gamma, stays at or below ``gi_max`` (these
+        grow like nu u^2 / gamma^3 and destabilise viscous, strongly
+        preconditioned cases; u_max = U for a cavity, 3U for a channel).
+    With nu = U L / Re the second bound is a cube-root cap on U.
     """
     rng = SplitMix64(seed)
     cases = []
@@ -202,9 +212,14 @@ def draw_cases(n: int, seed: int, side_lo=64, side_hi=512, re_lo=50.0, re_hi=100
         gamma = math.exp(rng.uniform(math.log(gamma_lo), math.log(gamma_hi)))
         nx, ny = (s, s) if kind == "cavity" else (4 * s, s)
         mask = random_obstacles(rng, nx, ny, kind)
-        u = u_ref
-        if u_over_gamma_max is not None:
-            u = min(u_ref, u_over_gamma_max * gamma)
+        cs_g = math.sqrt(gamma / 3.0)
+        accel = 1.0 if kind == "cavity" else 3.0
+        gi_cap = (gi_max * re * gamma /
+                  (3.0 * nx * (4.0 / gamma ** 2 - 1.0 / gamma) * accel ** 2)) ** (1.0 / 3.0)
+        if kind == "cavity":
+            u = min(u_cavity, ma_cavity * cs_g, gi_cap)
+        else:
+            u = min(u_channel, ma_channel * cs_g, gi_cap)
         cases.append(Case(kind, nx, ny, re, gamma, u, mask))
     return cases
 
