@@ -113,7 +113,7 @@ def time_to_steady(lbm, n_cases, side_hi, max_steps, seed=1806, tol=1e-8):
     steps_b, st_b, t_batch = steady.run_batch(b, tol=tol, max_steps=max_steps)
     b.close()
     print(f"[bench] batch {t_batch:.2f} s; plain runs", file=sys.stderr, flush=True)
-    t_plain, same, status = 0.0, True, {}
+    t_plain, status, mismatch = 0.0, {}, []
     names = {1: "converged", 3: "diverged", 0: "max_steps", 2: "plateau"}
     for i, k in enumerate(cases):
         lat = lbm.Lattice(k.nx, k.ny, k.sides, solid=k.mask, storage="f64", check_every=100,
@@ -122,7 +122,13 @@ def time_to_steady(lbm, n_cases, side_hi, max_steps, seed=1806, tol=1e-8):
         r = steady.run_single(lat, tol=tol, max_steps=max_steps)
         lat.close()
         t_plain += r.seconds
-        same &= (r.steps == int(steps_b[i]) and r.status == names[int(st_b[i])])
+        # diverging cases blow up at a step that depends on last-bit rounding
+        # (the two drivers' kernels contract FMAs differently): only their
+        # outcome must agree
+        if r.status != names[int(st_b[i])] or (r.status != "diverged" and
+                                                r.steps != int(steps_b[i])):
+            mismatch.append({"case": i, "plain": [r.steps, r.status],
+                             "batch": [int(steps_b[i]), names[int(st_b[i])]]})
         status[r.status] = status.get(r.status, 0) + 1
     return {"tol": tol, "storage": "f64", "cases": n_cases,
             "sample": f"seeded mix (seed {seed}) of cavities s x s and channels 4s x s, s in "
@@ -131,7 +137,7 @@ def time_to_steady(lbm, n_cases, side_hi, max_steps, seed=1806, tol=1e-8):
             "plain_s": round(t_plain, 3), "batch_s": round(t_batch, 3),
             "speedup": round(t_plain / t_batch, 3), "status": status,
             "batch_launch": {"block_height": choice[0], "schedule": choice[1]},
-            "same_steps_and_outcome": bool(same), "warm_start": None}
+            "same_steps_and_outcome": not mismatch, "mismatch": mismatch, "warm_start": None}
 
 
 def main():

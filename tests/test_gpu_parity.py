@@ -227,18 +227,66 @@ def test_reduced_storage_error_vs_oracle(lbm, storage, tol):
     assert err < tol
 
 
-def test_full_size_cavity_1024_fp32_against_oracle(lbm):
-    """Config C2 size (1024^2, Re 1000) in the default launch shape: all nodes
-    after 20 steps against the oracle run at the same size."""
+@pytest.fixture(scope="module")
+def oracle_1024():
     n, U = 1024, 0.1
-    _say("C2 1024^2 f32 20 steps")
-    o, g = run_pair(lbm, n, n, cavity_sides(), 20, storage="f32", nu=U * n / 1000, gamma=0.5,
-                    u_lid=U)
-    _, uxo, uyo = o.fields()
-    _, uxg, uyg = g.fields()
-    err = max(np.abs(uxg - uxo).max(), np.abs(uyg - uyo).max()) / U
-    _say("C2 max|du|/U", err)
-    assert err <= 1e-5
+    o = oracle.Oracle(n, n, cavity_sides(), nu=U * n / 1000, gamma=0.5, u_lid=U)
+    o.step(20)
+    return o.fields()
+
+
+def test_full_size_cavity_1024_fp32_against_oracle(lbm, oracle_1024):
+    """The 1024^2 Re 1000 cavity the benchmark times, in every launch shape
+    the autotuner can pick: all nodes after 20 steps against the oracle."""
+    n, U = 1024, 0.1
+    _, uxo, uyo = oracle_1024
+    for shape in lbm.launch_shapes():
+        _say("1024^2 f32 20 steps, launch", shape)
+        g = lbm.Lattice(n, n, cavity_sides(), storage="f32", nu=U * n / 1000, gamma=0.5,
+                        u_lid=U, check_every=100)
+        g.set_launch(*shape)
+        g.step(20)
+        _, uxg, uyg = g.fields()
+        g.close()
+        err = max(np.abs(uxg - uxo).max(), np.abs(uyg - uyo).max()) / U
+        _say("max|du|/U", err)
+        assert err <= 1e-5, shape
+
+
+@pytest.mark.parametrize("gamma", [1.0, 0.5])
+def test_gi_shear_wave_2048_full_size(lbm, gamma):
+    """Full-size GI check (2048^2 periodic, a = 1e-3, m = 16): with the
+    corrections the decay rate of the diagonal wave matches the closed form
+    (1/3)(1/w4 - 1/2) 2 k^2 for every background Ux; without them it shifts
+    by several per cent at Ux = 0.1 (a property that holds at any size; the
+    oracle pins it at small sizes)."""
+    n, m, nu = 2048, 16, 0.05 * gamma
+    k = 2 * math.pi * m / n
+    exact = nu / gamma * 2 * k * k          # (1/3)(1/w4 - 1/2) = nu / gamma
+    x = np.arange(n) + 0.5
+    rates = {}
+    for gi, ux0 in ((1, 0.0), (1, 0.05), (1, 0.1), (0, 0.1)):
+        _say("2048^2 shear wave gamma", gamma, "gi", gi, "Ux", ux0)
+        g = lbm.Lattice(n, n, periodic_sides(), storage="f32", nu=nu, gamma=gamma,
+                        gi_correct=gi, check_every=100)
+        g.init_fields(*diagonal_shear_wave(n, 1e-3, m, ux0))
+        ts, la = [], []
+        for _ in range(8):
+            g.step(500)
+            _, ux, uy = g.fields()
+            ts.append(g.steps)
+            # the wave is constant along x + y = const: the diagonal j = i
+            # (x = y) samples every phase; project on exp(i k (x + y))
+            d = (ux - uy)[np.arange(n), np.arange(n)] / math.sqrt(2)
+            la.append(math.log(abs((d * np.exp(-2j * k * x)).mean())))
+        g.close()
+        ts, la = np.array(ts), np.array(la)
+        rates[(gi, ux0)] = -np.polyfit(ts[1:], la[1:], 1)[0]
+    _say("rates", rates, "exact", exact)
+    for ux0 in (0.0, 0.05, 0.1):
+        assert abs(rates[(1, ux0)] - exact) < 0.01 * exact, ux0
+    # uncorrected defect: relative shift of order 3 Ux^2 / gamma^2
+    assert abs(rates[(0, 0.1)] - exact) > 0.5 * 3 * 0.1 ** 2 / gamma ** 2 * exact
 
 
 def test_unstable_run_reports_error(lbm):

@@ -1,0 +1,214 @@
+"""GPU tests of the U-Net kernels against the NumPy FP64 reference.
+
+Inputs are rounded to bf16 once and fed to both sides; the device
+accumulates in FP32, so FP32 outputs are compared within a bound
+proportional to the sum of absolute products, bf16 outputs within one bf16
+ulp (2^-8 relative) on top of that."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import unet_ref as R
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def U():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1806_10251_amd import unet
+    unet.load()
+    return unet
+
+
+def dev(a, dtype):
+    import torch
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.float().cpu().numpy().astype(np.float64)
+
+
+def bf(rng, *shape, scale=1.0):
+    return R.bf16(rng.standard_normal(shape) * scale)
+
+
+@pytest.mark.parametrize("n,h,w,cin,cout,ld_extra", [
+    (2, 12, 20, 64, 96, 0),      # ragged pixel count, 32-channel output tiles
+    (1, 16, 16, 32, 64, 32),     # 64-channel output tiles, input with ld > cin
+    (3, 8, 8, 384, 128, 0),      # concatenated input width of the decoder
+])
+def test_conv_forward(U, n, h, w, cin, cout, ld_extra):
+    import torch
+    _say("conv fwd", n, h, w, cin, cout, ld_extra)
+    rng = np.random.default_rng(10)
+    xfull = bf(rng, n, h, w, cin + ld_extra)
+    x = xfull[..., :cin]
+    wt = bf(rng, cout, 9, cin, scale=0.1)
+    b = rng.standard_normal(cout).astype(np.float32).astype(np.float64)
+    ref = R.conv3x3(x, wt, b)
+    bound = R.conv3x3(np.abs(x), np.abs(wt)) + np.abs(b)
+    xd = dev(xfull, torch.bfloat16)
+    y = U.conv3x3_fwd(xd, dev(wt, torch.bfloat16), dev(b, torch.float32), cout, out_f32=True)
+    err = np.abs(host(y) - ref)
+    assert (err <= 1e-5 * bound + 1e-6).all(), err.max()
+    yr = U.conv3x3_fwd(xd, dev(wt, torch.bfloat16), dev(b, torch.float32), cout, relu=True)
+    refr = np.maximum(ref, 0)
+    err = np.abs(host(yr) - refr)
+    assert (err <= 2 ** -8 * np.abs(refr) + 1e-5 * bound + 1e-6).all(), err.max()
+
+
+@pytest.mark.parametrize("n,h,w,cin,cout", [(2, 12, 20, 64, 32), (1, 16, 16, 128, 256)])
+def test_conv_backward_data(U, n, h, w, cin, cout):
+    import torch
+    _say("conv bwd data", n, h, w, cin, cout)
+    rng = np.random.default_rng(11)
+    dy = bf(rng, n, h, w, cout)
+    wt = bf(rng, cout, 9, cin, scale=0.1)
+    ref = R.conv3x3_bwd_data(dy, wt)
+    bound = R.conv3x3_bwd_data(np.abs(dy), np.abs(wt))
+    dx = U.conv3x3_bwd_data(dev(dy, torch.bfloat16), dev(wt, torch.bfloat16), cin)
+    err = np.abs(host(dx) - ref)
+    assert (err <= 2 ** -8 * np.abs(ref) + 1e-5 * bound + 1e-6).all(), err.max()
+
+
+@pytest.mark.parametrize("n,h,w,cin,cout", [
+    (2, 12, 20, 64, 32),     # pixel count not a multiple of the split size
+    (4, 64, 64, 32, 32),     # many splits
+    (2, 8, 8, 256, 256),     # bottom level
+])
+def test_conv_backward_weight(U, n, h, w, cin, cout):
+    import torch
+    _say("conv bwd weight", n, h, w, cin, cout)
+    rng = np.random.default_rng(12)
+    dy = bf(rng, n, h, w, cout)
+    x = bf(rng, n, h, w, cin)
+    dw_ref, db_ref = R.conv3x3_bwd_weight(dy, x)
+    bound, bb = R.conv3x3_bwd_weight(np.abs(dy), np.abs(x))
+    dw, db = U.conv3x3_bwd_weight(dev(dy, torch.bfloat16), dev(x, torch.bfloat16), cin, cout)
+    assert (np.abs(host(dw) - dw_ref) <= 1e-5 * bound + 1e-6).all()
+    assert (np.abs(host(db) - db_ref) <= 1e-5 * np.abs(dy).reshape(-1, cout).sum(0) + 1e-6).all()
+
+
+def test_pool_upsample_relu(U):
+    import torch
+    rng = np.random.default_rng(13)
+    x = bf(rng, 2, 8, 12, 64)
+    xd = dev(x, torch.bfloat16)
+    p = host(U.pool2_fwd(xd))
+    np.testing.assert_allclose(p, R.bf16(R.pool2(x)), rtol=2 ** -8, atol=1e-7)
+    up = host(U.up2_fwd(dev(R.bf16(R.pool2(x)), torch.bfloat16)))
+    np.testing.assert_array_equal(up, R.up2(R.bf16(R.pool2(x))))
+    g = bf(rng, 2, 4, 6, 64)
+    add = bf(rng, 2, 8, 12, 64)
+    pb = host(U.pool2_bwd(dev(g, torch.bfloat16), dev(add, torch.bfloat16)))
+    np.testing.assert_allclose(pb, add + R.pool2_bwd(g), rtol=2 ** -8, atol=1e-7)
+    ub = host(U.up2_bwd(dev(x, torch.bfloat16)))
+    np.testing.assert_allclose(ub, R.up2_bwd(x), rtol=2 ** -8, atol=1e-6)
+    d = dev(g, torch.bfloat16)
+    y = bf(rng, 2, 4, 6, 64)
+    U.relu_bwd(d, dev(y, torch.bfloat16))
+    np.testing.assert_array_equal(host(d), g * (y > 0))
+
+
+def test_loss_and_adam(U):
+    import torch
+    rng = np.random.default_rng(14)
+    out = rng.standard_normal((2, 8, 8, 32)).astype(np.float32).astype(np.float64)
+    t = rng.standard_normal((2, 8, 8, 3)).astype(np.float32).astype(np.float64)
+    fluid = (rng.random((2, 8, 8)) > 0.25).astype(np.uint8)
+    loss, dout = U.mse_loss(dev(out, torch.float32), dev(t, torch.float32),
+                            dev(fluid, torch.uint8))
+    lref, gref = R.mse_loss(out, t, fluid)
+    assert abs(loss - lref) <= 1e-12 * lref
+    np.testing.assert_allclose(host(dout), gref, rtol=2 ** -8, atol=1e-9)
+    p = rng.standard_normal(1000)
+    g = rng.standard_normal(1000)
+    pd, md, vd = dev(p, torch.float32), torch.zeros(1000, device="cuda"), torch.zeros(1000, device="cuda")
+    pr, mr, vr = p.astype(np.float32).astype(np.float64), np.zeros(1000), np.zeros(1000)
+    gf = g.astype(np.float32).astype(np.float64)
+    for step in (1, 2, 3):
+        U.adam(pd, md, vd, dev(gf, torch.float32), step, 1e-2)
+        pr, mr, vr = R.adam(pr, mr, vr, gf, step, 1e-2)
+    np.testing.assert_allclose(host(pd), pr, rtol=1e-5, atol=1e-6)
+
+
+def test_input_and_output_maps(U):
+    import torch
+    rng = np.random.default_rng(15)
+    solid = (rng.random((2, 32, 32)) > 0.8).astype(np.uint8)
+    cp = np.array([[100.0, 0.3, 0.05], [450.0, 1.0, 0.1]], np.float32)
+    x0 = host(U.make_input(dev(solid, torch.uint8), dev(cp, torch.float32), 16))
+    np.testing.assert_allclose(x0, R.bf16(R.make_input(solid, cp.astype(np.float64), 16)),
+                               rtol=2 ** -8, atol=0)
+    out = rng.standard_normal((2, 16, 16, 32)).astype(np.float32).astype(np.float64)
+    rho, ux, uy = U.fields_from_output(dev(out, torch.float32), dev(cp, torch.float32),
+                                       dev(solid, torch.uint8))
+    rr, ur, vr = R.fields_from_output(out, cp.astype(np.float64), solid)
+    np.testing.assert_allclose(host(rho), rr, rtol=0, atol=2e-6)
+    np.testing.assert_allclose(host(ux), ur, rtol=0, atol=1e-6)
+    np.testing.assert_allclose(host(uy), vr, rtol=0, atol=1e-6)
+
+
+def _net_inputs(res, n, seed):
+    rng = np.random.default_rng(seed)
+    solid = np.zeros((n, res, res), np.uint8)
+    solid[:, res // 4:res // 2, res // 3:res // 2] = 1
+    cp = np.array([[200.0 + 100 * k, 0.5, 0.1] for k in range(n)], np.float32)
+    x0 = R.bf16(R.make_input(solid, cp.astype(np.float64), res))
+    t = rng.standard_normal((n, res, res, 3)) * 0.5
+    return x0, t.astype(np.float32).astype(np.float64), (1 - solid).astype(np.uint8)
+
+
+def test_network_forward_and_gradients_match_reference(U):
+    import torch
+    res, n = 16, 2
+    _say("network fwd/bwd res", res, "batch", n)
+    x0, t, fluid = _net_inputs(res, n, 16)
+    net = U.UNet(max_batch=4, res=res, seed=123)
+    params = net.params().astype(np.float64)
+    out = host(net.forward(dev(x0, torch.bfloat16)))
+    ref, _ = R.forward(params, x0, round_acts=True)
+    rel = np.linalg.norm(out - ref) / np.linalg.norm(ref)
+    _say("forward rel L2", rel)
+    assert rel < 2e-2
+    loss = net.backward(dev(x0, torch.bfloat16), dev(t, torch.float32), dev(fluid, torch.uint8))
+    lref, gref = R.backward(params, x0, t, fluid, round_acts=True)
+    assert abs(loss - lref) < 2e-2 * lref
+    g = net.grads().astype(np.float64)
+    lay, _ = R.param_layout()
+    for k, (w_off, b_off, ci, co) in enumerate(lay):
+        a, b = g[w_off:w_off + 9 * ci * co], gref[w_off:w_off + 9 * ci * co]
+        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        _say("layer", k, "weight-grad rel L2", rel)
+        assert rel < 6e-2, k
+    net.close()
+
+
+def test_training_reduces_the_loss(U):
+    import torch
+    res, n = 32, 4
+    x0, _, fluid = _net_inputs(res, n, 17)
+    c = (np.arange(res) + 0.5) / res
+    X, Y = np.meshgrid(c, c)
+    t = np.stack([np.sin(2 * np.pi * X) * np.cos(np.pi * Y), X * Y, Y - 0.5], axis=-1)
+    t = np.broadcast_to(t, (n, res, res, 3)).astype(np.float32).astype(np.float64)
+    net = U.UNet(max_batch=n, res=res, seed=7)
+    xd, td, fd = dev(x0, torch.bfloat16), dev(t, torch.float32), dev(fluid, torch.uint8)
+    first = net.train_step(xd, td, fd, 1e-3)
+    for _ in range(60):
+        last = net.train_step(xd, td, fd, 1e-3)
+    _say("loss", first, "->", last)
+    assert last < 0.6 * first
+    net.close()
