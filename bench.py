@@ -92,12 +92,58 @@ def _case_kw(k):
     return dict(nu=k.nu, gamma=k.gamma, **kw)
 
 
-def time_to_steady(lbm, n_cases, side_hi, max_steps, seed=1806, tol=1e-8):
-    """Plain (one case after another) versus batched time to steady state."""
+WEIGHTS = os.path.join(ROOT, "paper_1806_10251_amd", "weights", "unet_cavity128.npy")
+
+
+def _batch_arm(lbm, cases, choice, tol, max_steps, warm_net=None, filter_at=()):
+    """One batched run of every case to tol: optional warm start (the
+    network's prediction, computed inside the timed region) and filter
+    steps.  Returns (steps, status, seconds, [(ux, uy)] per case)."""
     import numpy as np
     import torch
 
-    from paper_1806_10251_amd import autotune, steady
+    from paper_1806_10251_amd import autotune, steady, surrogate
+
+    grids = [lbm.make_grid(k.nx, k.ny, k.sides) for k in cases]
+    params = [lbm.make_params(storage="f64", check_every=100, **_case_kw(k)) for k in cases]
+    b = lbm.Batch(grids, [k.mask for k in cases], params)
+    autotune.apply_batch_choice(b, choice)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    if warm_net is not None:
+        surrogate.warm_init(warm_net, cases)(0, len(cases), b)
+    done = 0
+    for at in filter_at:
+        b.run(0.0, at - done)
+        done = at
+        b.average_last_two()
+    steps, st, _ = steady.run_batch(b, tol=tol, max_steps=max_steps - done)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    fields = [b.fields(i, k.ny, k.nx)[1:] for i, k in enumerate(cases)]
+    b.close()
+    return np.where(st == 3, steps, steps + done), st, sec, fields
+
+
+def _accuracy(cases, fields, ref, ok):
+    """max |u - u_ref| / U over the cases in ok."""
+    import numpy as np
+    errs = [max(np.abs(fields[i][0] - ref[i][0]).max(), np.abs(fields[i][1] - ref[i][1]).max()) /
+            cases[i].u_ref for i in ok]
+    return float(max(errs)) if errs else None
+
+
+def time_to_steady(lbm, n_cases, side_hi, max_steps, seed=1806, tol=1e-8):
+    """Time to steady state of a sample of the batched workload: the plain
+    method (one case after another, cold start), the batch (cold), the batch
+    with the two-step filter (cold), and the batch with the learned warm start
+    and the filter.  Each arm's converged fields are compared with a tighter
+    run (residual 1e-11) of the same cases."""
+    import numpy as np
+    import torch
+
+    from paper_1806_10251_amd import autotune, steady, surrogate
+    from paper_1806_10251_amd import unet as U
     from workloads import draw_cases
 
     cases = draw_cases(n_cases, seed, side_lo=64, side_hi=side_hi)
@@ -107,21 +153,31 @@ def time_to_steady(lbm, n_cases, side_hi, max_steps, seed=1806, tol=1e-8):
     print(f"[bench] time-to-steady: {n_cases} cases, {sum(k.nx * k.ny for k in cases)} nodes; "
           "tuning the batch", file=sys.stderr, flush=True)
     choice, _ = autotune.tune_batch(grids, masks, params, steps=200)
-    b = lbm.Batch(grids, masks, params)
-    autotune.apply_batch_choice(b, choice)
-    torch.cuda.synchronize()
-    steps_b, st_b, t_batch = steady.run_batch(b, tol=tol, max_steps=max_steps)
-    b.close()
-    print(f"[bench] batch {t_batch:.2f} s; plain runs", file=sys.stderr, flush=True)
-    t_plain, status, mismatch = 0.0, {}, []
+    arms = {}
+    steps_b, st_b, t_batch, f_batch = _batch_arm(lbm, cases, choice, tol, max_steps)
+    arms["batch"] = (steps_b, st_b, t_batch, f_batch)
+    print(f"[bench] batch {t_batch:.2f} s; reference run to 1e-11", file=sys.stderr, flush=True)
+    _, st_ref, _, f_ref = _batch_arm(lbm, cases, choice, 1e-11, 4 * max_steps)
+    arms["batch+filter"] = _batch_arm(lbm, cases, choice, tol, max_steps,
+                                      filter_at=surrogate.WARM_FILTER)
+    net = None
+    if os.path.exists(WEIGHTS):
+        net = U.UNet(max_batch=16, res=surrogate.RES, seed=0)
+        surrogate.load_into(net, WEIGHTS)
+        arms["batch+surrogate"] = _batch_arm(lbm, cases, choice, tol, max_steps, warm_net=net,
+                                             filter_at=surrogate.WARM_FILTER)
+    print("[bench] plain runs", file=sys.stderr, flush=True)
+    t_plain, status, mismatch, f_plain, steps_p = 0.0, {}, [], [], []
     names = {1: "converged", 3: "diverged", 0: "max_steps", 2: "plateau"}
     for i, k in enumerate(cases):
         lat = lbm.Lattice(k.nx, k.ny, k.sides, solid=k.mask, storage="f64", check_every=100,
                           **_case_kw(k))
         torch.cuda.synchronize()
         r = steady.run_single(lat, tol=tol, max_steps=max_steps)
+        f_plain.append(lat.fields()[1:])
         lat.close()
         t_plain += r.seconds
+        steps_p.append(r.steps)
         # diverging cases blow up at a step that depends on last-bit rounding
         # (the two drivers' kernels contract FMAs differently): only their
         # outcome must agree
@@ -130,14 +186,33 @@ def time_to_steady(lbm, n_cases, side_hi, max_steps, seed=1806, tol=1e-8):
             mismatch.append({"case": i, "plain": [r.steps, r.status],
                              "batch": [int(steps_b[i]), names[int(st_b[i])]]})
         status[r.status] = status.get(r.status, 0) + 1
-    return {"tol": tol, "storage": "f64", "cases": n_cases,
-            "sample": f"seeded mix (seed {seed}) of cavities s x s and channels 4s x s, s in "
-                      f"[64, {side_hi}], 1-4 rectangular obstacles covering 5-20%, Re in "
-                      f"[50, 1000], gamma log-uniform in [0.05, 1]; at most {max_steps} steps",
-            "plain_s": round(t_plain, 3), "batch_s": round(t_batch, 3),
-            "speedup": round(t_plain / t_batch, 3), "status": status,
-            "batch_launch": {"block_height": choice[0], "schedule": choice[1]},
-            "same_steps_and_outcome": not mismatch, "mismatch": mismatch, "warm_start": None}
+    ok = [i for i in range(n_cases) if st_ref[i] == 1 and st_b[i] == 1]
+    out = {"tol": tol, "storage": "f64", "cases": n_cases,
+           "sample": f"seeded mix (seed {seed}) of cavities s x s and channels 4s x s, s in "
+                     f"[64, {side_hi}], 1-4 rectangular obstacles covering 5-20%, Re in "
+                     f"[50, 1000], gamma log-uniform in [0.05, 1]; at most {max_steps} steps",
+           "plain_s": round(t_plain, 3), "batch_s": round(t_batch, 3),
+           "speedup": round(t_plain / t_batch, 3), "status": status,
+           "batch_launch": {"block_height": choice[0], "schedule": choice[1]},
+           "same_steps_and_outcome": not mismatch, "mismatch": mismatch,
+           "accuracy_ref": "max |u - u_ref| / U over cases converged in both, u_ref from a "
+                           "batched run to residual 1e-11",
+           "arms": {"plain": {"seconds": round(t_plain, 3), "steps": int(np.sum(steps_p)),
+                              "max_err": _accuracy(cases, f_plain, f_ref, ok)}}}
+    for name, (stp, st, sec, flds) in arms.items():
+        out["arms"][name] = {"seconds": round(sec, 3), "steps": int(np.sum(stp)),
+                             "converged": int((st == 1).sum()),
+                             "max_err": _accuracy(cases, flds, f_ref, [i for i in ok if st[i] == 1]),
+                             "speedup_vs_plain": round(t_plain / sec, 3)}
+    if net is not None:
+        out["warm_start"] = {"weights": os.path.relpath(WEIGHTS, ROOT),
+                             "covers": "square cavities (channels keep the cold start)",
+                             "filter_steps": list(surrogate.WARM_FILTER),
+                             **out["arms"]["batch+surrogate"]}
+        net.close()
+    else:
+        out["warm_start"] = None
+    return out
 
 
 def main():

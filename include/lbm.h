@@ -112,6 +112,16 @@ int lbm_set_stream(lbm_ctx* ctx, void* hip_stream);
  * steady-state residual and the mass. */
 int lbm_step(lbm_ctx* ctx, int64_t n);
 
+/* Replace the current state by the mean of the two lattices: after
+ * lbm_step(n >= 1) they hold the states of the last two steps (after an
+ * initialisation, the initial state twice).  Every undamped period-2
+ * component of the state (eigenvalue -1 of the step map, such as the
+ * staggered momenta that bounce-back lattices keep) cancels, a
+ * steady state is left unchanged, and the fixed point of the iteration is
+ * the same.  Meant for warm starts from predicted fields, which excite such
+ * components while the state at rest does not.  Asynchronous. */
+int lbm_average_last_two(lbm_ctx* ctx);
+
 /* Residual of the last check step, sqrt(sum |u^{n+1}-u^n|^2 / sum |u^n|^2)
  * over fluid nodes.  Synchronises.  LBM_ESTATE before the first check step;
  * LBM_EUNSTABLE (and *r set) when it is not finite. */
@@ -210,6 +220,9 @@ int lbm_batch_set_enabled(lbm_batch* b, const int32_t* enabled);
 
 /* Convert every case's state to LBM_STORE_F32 or LBM_STORE_F64 in place. */
 int lbm_batch_set_storage(lbm_batch* b, int32_t storage);
+
+/* For every enabled case, as lbm_average_last_two. */
+int lbm_batch_average_last_two(lbm_batch* b);
 
 /* Residual of case c at its last check step. */
 int lbm_batch_residual(lbm_batch* b, int32_t c, double* r);

@@ -103,8 +103,9 @@ int unet_adam(float* p, float* m, float* v, const float* g, void* pb, int64_t co
               double beta1, double beta2, double eps, int64_t t, void* stream);
 
 /* Network input from geometry and flow parameters: for case i the solid
- * mask (u8, [n][fine][fine], fine a multiple of res) is averaged over
- * (fine/res)^2 blocks to a solid fraction at res x res; case_params[i] =
+ * mask (u8, [n][fine][fine], any fine >= 1) becomes a solid fraction at
+ * res x res (coarse cell I covers the fine nodes floor(I fine/res) ..
+ * floor((I+1) fine/res) - 1, at least one node); case_params[i] =
  * {Re, gamma, U} (FP32, device).  x0: bf16 [n][res][res][UNET_IN_CHANNELS]:
  * channel 0 solid fraction, 1 Re/500, 2 gamma, 3 U/0.1, 4 x, 5 y (node
  * centres scaled to (0, 1)), 6 one on the top row (lid), 7 one; rest 0. */
@@ -113,8 +114,13 @@ int unet_make_input(const uint8_t* solid, int32_t fine, const float* case_params
 
 /* Lattice fields from the network output (FP32 [n][res][res][ldo]):
  * bilinear interpolation to the fine grid, rho = 1 + 3 U^2 o0,
- * u = U (o1, o2); solid nodes get rho = 1, u = 0; the fluid mean of rho - 1
- * is removed per case so that the warm start holds the cold start's mass.
+ * u = U (o1, o2); solid nodes get rho = 1, u = 0.  Per case, the fluid mean
+ * of rho - 1 is removed (the warm start holds the cold start's mass), and
+ * so are the staggered momenta sum (-1)^i rho u_x and sum (-1)^j rho u_y
+ * (u_x -= (-1)^i c_x, c_x = sum (-1)^i rho u_x / sum rho; likewise u_y):
+ * with bounce-back walls every step flips their sign, so a start that
+ * carries them keeps an undamped period-2 oscillation and never reaches a
+ * steady state, while the state at rest carries none.
  * rho, ux, uy: FP32 device [n][fine][fine]. */
 int unet_fields_from_output(const float* out, int32_t ldo, int32_t n, int32_t res,
                             const float* case_params, const uint8_t* solid, int32_t fine,

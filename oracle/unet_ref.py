@@ -229,8 +229,10 @@ def make_input(solid, case_params, res):
     """Network input as defined for the device (channels 0-7 used)."""
     solid = np.asarray(solid)
     n, fine, _ = solid.shape
-    f = fine // res
-    frac = solid.reshape(n, res, f, res, f).astype(np.float64).mean(axis=(2, 4))
+    lo = [I * fine // res for I in range(res)]
+    hi = [max((I + 1) * fine // res, lo[I] + 1) for I in range(res)]
+    frac = np.array([[[solid[k, lo[J]:hi[J], lo[I]:hi[I]].astype(np.float64).mean()
+                       for I in range(res)] for J in range(res)] for k in range(n)])
     x = np.zeros((n, res, res, IN_CHANNELS))
     cp = np.asarray(case_params, np.float64)
     c = (np.arange(res) + 0.5) / res
@@ -249,7 +251,10 @@ def fields_from_output(out, case_params, solid):
     """Lattice fields from the network output: bilinear interpolation of the
     coarse pixel-centred output to the fine node centres (clamped at the
     border), rho = 1 + 3 U^2 o0, u = U (o1, o2); solid nodes rho = 1, u = 0;
-    then the fluid mean of rho - 1 is removed per case."""
+    then per case the fluid mean of rho - 1 is removed and, with it removed,
+    the staggered momenta: u_x -= (-1)^i sum((-1)^i rho u_x) / sum(rho) over
+    the fluid (likewise u_y with (-1)^j); these two sums change sign every
+    step of a bounce-back lattice and must start at zero."""
     out = np.asarray(out, np.float64)
     solid = np.asarray(solid, bool)
     n, res = out.shape[0], out.shape[1]
@@ -271,5 +276,12 @@ def fields_from_output(out, case_params, solid):
         s = solid[k]
         r[s], a[s], b[s] = 1.0, 0.0, 0.0
         r[~s] -= (r[~s] - 1).mean()
+        sx = np.where(np.arange(fine) % 2 == 0, 1.0, -1.0)[None, :]
+        sy = np.where(np.arange(fine) % 2 == 0, 1.0, -1.0)[:, None]
+        R = r[~s].sum()
+        cx = (sx * r * a)[~s].sum() / R
+        cy = (sy * r * b)[~s].sum() / R
+        a = np.where(s, 0.0, a - sx * cx)
+        b = np.where(s, 0.0, b - sy * cy)
         rho[k], ux[k], uy[k] = r, a, b
     return rho, ux, uy

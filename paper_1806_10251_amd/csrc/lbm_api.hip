@@ -438,6 +438,16 @@ static int read_result(lbm_ctx* c, double r[4]) {
   return LBM_OK;
 }
 
+int lbm_average_last_two(lbm_ctx* c) {
+  if (!c) return fail(LBM_EINVAL, "null context");
+  const Geom g = make_geom(c);
+  const long long n = 9LL * g.plane;
+  HIPCHECK(launch_average(c->p.storage, c->lat[c->cur], c->lat[c->cur ^ 1], n,
+                          (double)c->kf.scale, c->hist[c->cur], c->hist[c->cur ^ 1],
+                          c->hist[0] ? 2LL * c->grid.ny : 0, c->stream));
+  return LBM_OK;
+}
+
 int lbm_residual(lbm_ctx* c, double* r) {
   if (!c || !r) return fail(LBM_EINVAL, "null argument");
   double v[4];

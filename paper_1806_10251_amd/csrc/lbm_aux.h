@@ -5,9 +5,73 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "lbm_device.h"
 
 namespace lbmk {
+
+// cur = (cur + prev) / 2 over whole lattices (frame and solid slots too), in
+// the compute precision of the storage type.  Boundary slots hold linear
+// functions of the node populations plus constants, so the mean is again a
+// consistent lattice.
+template <class S>
+__global__ __launch_bounds__(256) void average_kernel(typename S::T* __restrict__ cur,
+                                                      const typename S::T* __restrict__ prev,
+                                                      long long n, typename S::C scale,
+                                                      typename S::C inv_scale) {
+  using C = typename S::C;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x) {
+    const C a = S::dec(cur[i], inv_scale), b = S::dec(prev[i], inv_scale);
+    cur[i] = S::enc(C(0.5) * (a + b), scale);
+  }
+}
+
+template <class C>
+__global__ __launch_bounds__(256) void average_plain_kernel(C* __restrict__ cur,
+                                                            const C* __restrict__ prev,
+                                                            long long n) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x)
+    cur[i] = C(0.5) * (cur[i] + prev[i]);
+}
+
+// Launch average_kernel for a storage code (LBM_STORE_*); history arrays
+// (outlet velocity, compute type) are averaged too when present.
+inline hipError_t launch_average(int storage, void* cur, const void* prev, long long n,
+                                 double scale, void* hcur, const void* hprev, long long nh,
+                                 hipStream_t st) {
+  const int blocks = (int)std::min<long long>((n + 255) / 256, 8192);
+  switch (storage) {
+    case 0:
+      hipLaunchKernelGGL(average_kernel<StoreF64>, dim3(blocks), dim3(256), 0, st, (double*)cur,
+                         (const double*)prev, n, 1.0, 1.0);
+      break;
+    case 1:
+      hipLaunchKernelGGL(average_kernel<StoreF32>, dim3(blocks), dim3(256), 0, st, (float*)cur,
+                         (const float*)prev, n, 1.f, 1.f);
+      break;
+    case 2:
+      hipLaunchKernelGGL(average_kernel<StoreBF16>, dim3(blocks), dim3(256), 0, st,
+                         (uint16_t*)cur, (const uint16_t*)prev, n, (float)scale,
+                         (float)(1.0 / scale));
+      break;
+    default:
+      hipLaunchKernelGGL(average_kernel<StoreF16>, dim3(blocks), dim3(256), 0, st,
+                         (_Float16*)cur, (const _Float16*)prev, n, (float)scale,
+                         (float)(1.0 / scale));
+      break;
+  }
+  if (hcur && hprev && nh > 0) {
+    const int hb = (int)std::min<long long>((nh + 255) / 256, 1024);
+    if (storage == 0)
+      hipLaunchKernelGGL(average_plain_kernel<double>, dim3(hb), dim3(256), 0, st, (double*)hcur,
+                         (const double*)hprev, nh);
+    else
+      hipLaunchKernelGGL(average_plain_kernel<float>, dim3(hb), dim3(256), 0, st, (float*)hcur,
+                         (const float*)hprev, nh);
+  }
+  return hipGetLastError();
+}
 
 // Fixed-order sum of the per-tile partials: out[0..3].
 template <int kThreads = 256>

@@ -920,6 +920,21 @@ int lbm_batch_set_storage(lbm_batch* b, int32_t storage) {
   return configure(b);
 }
 
+int lbm_batch_average_last_two(lbm_batch* b) {
+  if (!b) return fail(LBM_EINVAL, "null batch");
+  for (int i = 0; i < b->n; ++i) {
+    if (!b->enabled[i]) continue;
+    HostCase& h = b->cs[i];
+    const int cur = h.state_par;
+    const long long n = 9LL * h.g.plane;
+    HIPCHECK(launch_average(b->storage, h.lat[cur], h.lat[cur ^ 1], n, (double)h.kf.scale,
+                            h.hist[cur], h.hist[cur ^ 1], h.hist[0] ? 2LL * h.grid.ny : 0,
+                            b->stream));
+  }
+  HIPCHECK(hipStreamSynchronize(b->stream));
+  return LBM_OK;
+}
+
 int lbm_batch_residual(lbm_batch* b, int32_t ci, double* r) {
   if (!b || !r || ci < 0 || ci >= b->n) return fail(LBM_EINVAL, "bad argument");
   double v[4];

@@ -484,22 +484,32 @@ __global__ void to_bf16_kernel(const float* p, bf16* pb, long long n) {
 // ---------------------------------------------------------------------------
 // Input and output maps
 // ---------------------------------------------------------------------------
+// Coarse cell I covers the fine nodes i with floor(I fine / res) <= i <
+// floor((I + 1) fine / res) (at least the node floor(I fine / res)); its
+// solid fraction is the mean of the mask over those nodes.
+__device__ __forceinline__ void cell_range(int I, int fine, int res, int& a, int& b) {
+  a = int((long long)I * fine / res);
+  b = int((long long)(I + 1) * fine / res);
+  if (b <= a) b = a + 1;
+}
+
 __global__ void make_input_kernel(const uint8_t* solid, int fine, const float* cp, int n, int res,
                                   bf16* x0) {
   const long long total = (long long)n * res * res;
-  const int f = fine / res;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
        e += (long long)gridDim.x * blockDim.x) {
     const int i = int(e % res), j = int((e / res) % res);
     const long long c = e / ((long long)res * res);
+    int i0, i1, j0, j1;
+    cell_range(i, fine, res, i0, i1);
+    cell_range(j, fine, res, j0, j1);
     int cnt = 0;
-    for (int b = 0; b < f; ++b)
-      for (int a = 0; a < f; ++a)
-        cnt += solid[(c * fine + (long long)j * f + b) * fine + (long long)i * f + a] != 0;
+    for (int b = j0; b < j1; ++b)
+      for (int a = i0; a < i1; ++a) cnt += solid[(c * fine + b) * fine + a] != 0;
     float v[UNET_IN_CHANNELS];
 #pragma unroll
     for (int k = 0; k < UNET_IN_CHANNELS; ++k) v[k] = 0.f;
-    v[0] = float(cnt) / float(f * f);
+    v[0] = float(cnt) / float((i1 - i0) * (j1 - j0));
     v[1] = cp[3 * c + 0] / 500.f;
     v[2] = cp[3 * c + 1];
     v[3] = cp[3 * c + 2] / 0.1f;
@@ -552,31 +562,60 @@ __global__ void fields_kernel(const float* out, int ldo, int n, int res, const f
   }
 }
 
-// one block per case: remove the fluid mean of rho - 1 (fixed-order FP64 sum)
-__global__ __launch_bounds__(256) void mass_fix_kernel(float* rho, const uint8_t* solid,
-                                                       int fine) {
-  __shared__ double s[256], sn[256];
+// One block per case (fixed-order FP64 sums).  (1) Remove the fluid mean of
+// rho - 1.  (2) Remove the staggered momentum components: with bounce-back
+// walls and no force, every step flips the sign of
+// Ix = sum_fluid (-1)^i j_x and of Iy = sum_fluid (-1)^j j_y (collision
+// conserves j at each node; streaming and bounce-back move each population
+// with e_x != 0 to a column of the other parity, or reverse it in place), so
+// a start with Ix or Iy != 0 never settles: the state keeps an undamped
+// period-2 oscillation.  u_x -= (-1)^i Ix / sum rho (likewise u_y) makes
+// both zero, as they are for the state at rest.
+__global__ __launch_bounds__(256) void mass_fix_kernel(float* rho, float* ux, float* uy,
+                                                       const uint8_t* solid, int fine) {
+  __shared__ double s[4][256];
   const long long base = (long long)blockIdx.x * fine * fine;
   const long long cnt = (long long)fine * fine;
+  auto block_sum = [&](int q) {
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) s[q][threadIdx.x] += s[q][threadIdx.x + w];
+      __syncthreads();
+    }
+    return s[q][0];
+  };
   double acc = 0.0, nf = 0.0;
   for (long long k = threadIdx.x; k < cnt; k += 256)
     if (!solid[base + k]) {
       acc += (double)rho[base + k] - 1.0;
       nf += 1.0;
     }
-  s[threadIdx.x] = acc;
-  sn[threadIdx.x] = nf;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      s[threadIdx.x] += s[threadIdx.x + w];
-      sn[threadIdx.x] += sn[threadIdx.x + w];
-    }
-    __syncthreads();
-  }
-  const float mean = sn[0] > 0 ? float(s[0] / sn[0]) : 0.f;
+  s[0][threadIdx.x] = acc;
+  s[1][threadIdx.x] = nf;
+  const double sum_dr = block_sum(0), n_fluid = block_sum(1);
+  const float mean = n_fluid > 0 ? float(sum_dr / n_fluid) : 0.f;
+  double sx = 0.0, sy = 0.0, sr = 0.0;
   for (long long k = threadIdx.x; k < cnt; k += 256)
-    if (!solid[base + k]) rho[base + k] -= mean;
+    if (!solid[base + k]) {
+      const float r = rho[base + k] - mean;
+      rho[base + k] = r;
+      const int i = int(k % fine), j = int(k / fine);
+      sx += (i & 1 ? -1.0 : 1.0) * (double)r * (double)ux[base + k];
+      sy += (j & 1 ? -1.0 : 1.0) * (double)r * (double)uy[base + k];
+      sr += (double)r;
+    }
+  __syncthreads();
+  s[0][threadIdx.x] = sx;
+  s[1][threadIdx.x] = sy;
+  s[2][threadIdx.x] = sr;
+  const double Ix = block_sum(0), Iy = block_sum(1), R = block_sum(2);
+  const float mx = R > 0 ? float(Ix / R) : 0.f, my = R > 0 ? float(Iy / R) : 0.f;
+  for (long long k = threadIdx.x; k < cnt; k += 256)
+    if (!solid[base + k]) {
+      const int i = int(k % fine), j = int(k / fine);
+      ux[base + k] -= (i & 1) ? -mx : mx;
+      uy[base + k] -= (j & 1) ? -my : my;
+    }
 }
 
 }  // namespace
@@ -745,8 +784,8 @@ int unet_adam(float* p, float* m, float* v, const float* g, void* pb, int64_t co
 
 int unet_make_input(const uint8_t* solid, int32_t fine, const float* case_params, int32_t n,
                     int32_t res, void* x0, void* stream) {
-  if (!solid || !case_params || !x0 || n <= 0 || res <= 0 || fine < res || fine % res)
-    return fail(UNET_EINVAL, "make_input: bad arguments (fine must be a multiple of res)");
+  if (!solid || !case_params || !x0 || n <= 0 || res <= 0 || fine <= 0)
+    return fail(UNET_EINVAL, "make_input: bad arguments");
   hipLaunchKernelGGL(make_input_kernel, dim3(grid_for((long long)n * res * res)), dim3(256), 0,
                      as_stream(stream), solid, fine, case_params, n, res, static_cast<bf16*>(x0));
   UCHECK(hipGetLastError());
@@ -762,7 +801,7 @@ int unet_fields_from_output(const float* out, int32_t ldo, int32_t n, int32_t re
   hipStream_t st = as_stream(stream);
   hipLaunchKernelGGL(fields_kernel, dim3(grid_for((long long)n * fine * fine)), dim3(256), 0, st,
                      out, ldo, n, res, case_params, solid, fine, rho, ux, uy);
-  hipLaunchKernelGGL(mass_fix_kernel, dim3(n), dim3(256), 0, st, rho, solid, fine);
+  hipLaunchKernelGGL(mass_fix_kernel, dim3(n), dim3(256), 0, st, rho, ux, uy, solid, fine);
   UCHECK(hipGetLastError());
   return UNET_OK;
 }

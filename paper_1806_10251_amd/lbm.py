@@ -30,7 +30,7 @@ EXPORTS = (
     "lbm_batch_init_fields_device", "lbm_batch_set_stream", "lbm_batch_run",
     "lbm_batch_residual", "lbm_batch_fields", "lbm_batch_set_launch", "lbm_batch_destroy",
     "lbm_set_storage", "lbm_batch_set_plateau", "lbm_batch_status", "lbm_batch_set_enabled",
-    "lbm_batch_set_storage",
+    "lbm_batch_set_storage", "lbm_average_last_two", "lbm_batch_average_last_two",
 )
 
 
@@ -88,6 +88,8 @@ def load():
         "lbm_save": [vp, ctypes.c_char_p],
         "lbm_load": [vp, ctypes.c_char_p],
         "lbm_set_launch": [vp, i32, i32],
+        "lbm_average_last_two": [vp],
+        "lbm_batch_average_last_two": [vp],
         "lbm_get_launch": [vp, P(i32), P(i32)],
         "lbm_launch_shapes": [P(i32), i32],
         "lbm_set_timing": [vp, i32],
@@ -261,6 +263,10 @@ class Lattice:
     def load_checkpoint(self, path):
         _check(load().lbm_load(self._h, str(path).encode()))
 
+    def average_last_two(self):
+        """Replace the state by the mean of the last two steps' states."""
+        _check(load().lbm_average_last_two(self._h))
+
     # --- launch shape / timing ----------------------------------------------
     def set_launch(self, by, rows):
         _check(load().lbm_set_launch(self._h, int(by), int(rows)))
@@ -318,6 +324,10 @@ class Batch:
     def set_stream(self, stream):
         raw = getattr(stream, "cuda_stream", stream)
         _check(load().lbm_batch_set_stream(self._h, ctypes.c_void_p(raw) if raw else None))
+
+    def average_last_two(self):
+        """Every enabled case: state = mean of its last two steps' states."""
+        _check(load().lbm_batch_average_last_two(self._h))
 
     def set_launch(self, rows_per_item=0, schedule=0):
         """rows_per_item: block height 4, 8 or 16 (0 = 4); schedule 0 graph

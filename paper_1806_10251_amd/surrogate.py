@@ -6,14 +6,19 @@ from the lattice Boltzmann library itself (batched FP64 runs to residual
 library's BF16 MFMA kernels; the predicted (rho, u) initialise the lattice
 at their equilibrium, so the iteration and its fixed point are unchanged and
 only the starting point moves.  The cold start (rest state) remains the
-fallback: a case whose warm start does not converge is rerun cold.
+fallback for every case the network does not cover (anything but a square
+cavity).
 
 Targets (per fluid node): (rho - 1) / (3 U^2), u_x / U, u_y / U.  The
 network works at a fixed resolution (128 x 128); a larger lattice is
 described to it by the solid fraction of each coarse cell, and its output is
 interpolated bilinearly to the lattice (unet_fields_from_output), with the
 fluid mean of rho - 1 removed so that a closed cavity keeps the cold start's
-mass.
+mass and with the staggered momenta that bounce-back lattices never damp
+removed.  A warm-started state is also replaced, after its first step and
+after 1000 steps, by the mean of its last two steps (Batch.average_last_two):
+the prediction excites period-2 components that barely decay and would
+otherwise dominate the one-step residual.
 
 Command line (one GPU):
   python -m paper_1806_10251_amd.surrogate train --out weights.npy
@@ -52,10 +57,14 @@ def _lat_kw(k):
     return dict(nu=k.nu, gamma=k.gamma, u_lid=k.u_ref)
 
 
-def steady_fields(cases, tol=1e-8, max_steps=400000, chunk=512, init=None, log=None):
+def steady_fields(cases, tol=1e-8, max_steps=400000, chunk=512, init=None, filter_at=(),
+                  log=None):
     """Run every case to the residual tol with the batch (FP64).  init(i0,
-    i1, batch) may set initial fields of cases [i0, i1).  Returns (rho, ux,
-    uy, steps, status, seconds) with fields [n][ny][nx] (FP64, host)."""
+    i1, batch) may set initial fields of cases [i0, i1); filter_at: steps
+    after which the state is replaced by the mean of its last two steps
+    (Batch.average_last_two), before the run that checks the residual.
+    Returns (rho, ux, uy, steps, status, seconds) with fields [n][ny][nx]
+    (FP64, host); steps count from the start."""
     n = len(cases)
     ny, nx = cases[0].ny, cases[0].nx
     rho = np.zeros((n, ny, nx))
@@ -68,11 +77,22 @@ def steady_fields(cases, tol=1e-8, max_steps=400000, chunk=512, init=None, log=N
         grids = [L.make_grid(k.nx, k.ny, k.sides) for k in part]
         params = [L.make_params(storage="f64", check_every=100, **_lat_kw(k)) for k in part]
         b = L.Batch(grids, [k.mask for k in part], params)
+        import torch
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         if init is not None:
             init(i0, i0 + len(part), b)
-        s, st, sec = steady.run_batch(b, tol=tol, max_steps=max_steps)
+        done = 0
+        for at in sorted(filter_at):
+            if at > done:
+                b.run(0.0, at - done)
+                done = at
+            b.average_last_two()
+        s, st, _ = steady.run_batch(b, tol=tol, max_steps=max_steps - done)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
         secs += sec
-        steps[i0:i0 + len(part)] = s
+        steps[i0:i0 + len(part)] = np.where(st == 3, s, s + done)
         status[i0:i0 + len(part)] = st
         for j in range(len(part)):
             rho[i0 + j], ux[i0 + j], uy[i0 + j] = b.fields(j, ny, nx)
@@ -143,30 +163,47 @@ def evaluate_loss(net, data, batch):
 
 
 def predict_fields(net, cases):
-    """Device tensors rho, ux, uy [n][fine][fine] for square cases."""
+    """Predicted (rho, ux, uy) device tensors [ny][nx] per case; None for
+    cases that are not square cavities (the network was trained on those;
+    such cases keep the cold start).  Cases of one size share a forward
+    pass."""
     import torch
-    fine = cases[0].nx
-    solid = torch.tensor(np.stack([k.mask for k in cases]).astype(np.uint8), device="cuda")
-    cp = torch.tensor(case_params(cases), device="cuda")
-    x0 = U.make_input(solid, cp, RES)
-    rho = torch.empty((len(cases), fine, fine), device="cuda")
-    ux, uy = torch.empty_like(rho), torch.empty_like(rho)
-    for i0 in range(0, len(cases), net.max_batch):
-        i1 = min(len(cases), i0 + net.max_batch)
-        out = net.forward(x0[i0:i1].contiguous())
-        r, a, b = U.fields_from_output(out, cp[i0:i1].contiguous(), solid[i0:i1].contiguous())
-        rho[i0:i1], ux[i0:i1], uy[i0:i1] = r, a, b
-    return rho, ux, uy
+    out = [None] * len(cases)
+    by_size = {}
+    for i, k in enumerate(cases):
+        if k.kind == "cavity" and k.nx == k.ny:
+            by_size.setdefault(k.nx, []).append(i)
+    for fine, idx in by_size.items():
+        group = [cases[i] for i in idx]
+        solid = torch.tensor(np.stack([k.mask for k in group]).astype(np.uint8), device="cuda")
+        cp = torch.tensor(case_params(group), device="cuda")
+        x0 = U.make_input(solid, cp, RES)
+        for i0 in range(0, len(group), net.max_batch):
+            i1 = min(len(group), i0 + net.max_batch)
+            o = net.forward(x0[i0:i1].contiguous())
+            r, a, b = U.fields_from_output(o, cp[i0:i1].contiguous(), solid[i0:i1].contiguous())
+            for j in range(i1 - i0):
+                out[idx[i0 + j]] = (r[j].contiguous(), a[j].contiguous(), b[j].contiguous())
+    return out
+
+
+# Steps after which a warm-started state is replaced by the mean of its last
+# two steps: the prediction excites period-2 components (eigenvalue near -1
+# of the step map) that barely decay and dominate the one-step residual.
+WARM_FILTER = (1, 1000)
 
 
 def warm_init(net, cases):
-    """An init callback for steady_fields: equilibrium at the prediction."""
-    rho, ux, uy = predict_fields(net, cases)
+    """An init callback for steady_fields (and for any batch built from
+    `cases` in order): equilibrium at the prediction where there is one
+    (use with filter_at=WARM_FILTER)."""
+    pred = predict_fields(net, cases)
 
     def init(i0, i1, batch):
         for j in range(i1 - i0):
-            batch.init_fields_device(j, rho[i0 + j].contiguous(), ux[i0 + j].contiguous(),
-                                     uy[i0 + j].contiguous())
+            p = pred[i0 + j]
+            if p is not None:
+                batch.init_fields_device(j, *p)
     return init
 
 

@@ -149,9 +149,10 @@ def test_input_and_output_maps(U):
     rng = np.random.default_rng(15)
     solid = (rng.random((2, 32, 32)) > 0.8).astype(np.uint8)
     cp = np.array([[100.0, 0.3, 0.05], [450.0, 1.0, 0.1]], np.float32)
-    x0 = host(U.make_input(dev(solid, torch.uint8), dev(cp, torch.float32), 16))
-    np.testing.assert_allclose(x0, R.bf16(R.make_input(solid, cp.astype(np.float64), 16)),
-                               rtol=2 ** -8, atol=0)
+    for res in (16, 24, 48):          # coarser, not a divisor, finer than the mask
+        x0 = host(U.make_input(dev(solid, torch.uint8), dev(cp, torch.float32), res))
+        np.testing.assert_allclose(x0, R.bf16(R.make_input(solid, cp.astype(np.float64), res)),
+                                   rtol=2 ** -8, atol=0)
     out = rng.standard_normal((2, 16, 16, 32)).astype(np.float32).astype(np.float64)
     rho, ux, uy = U.fields_from_output(dev(out, torch.float32), dev(cp, torch.float32),
                                        dev(solid, torch.uint8))

@@ -119,3 +119,16 @@ def test_make_input_layout():
     assert x[0, 3, 3, 1] == 0.5 and x[0, 3, 3, 2] == 0.5 and x[0, 3, 3, 3] == 0.5
     assert x[0, 7, 2, 6] == 1.0 and x[0, 6, 2, 6] == 0.0
     assert np.all(x[..., 8:] == 0)
+
+
+def test_make_input_fraction_on_uneven_grids():
+    """Solid fraction = mean of the mask over the nodes of each coarse cell;
+    total solid area is kept when res divides fine, and every coarse cell
+    sees at least one node when res > fine."""
+    rng = np.random.default_rng(7)
+    solid = (rng.random((1, 20, 20)) > 0.6).astype(np.uint8)
+    x = U.make_input(solid, [[100.0, 0.5, 0.1]], 10)
+    np.testing.assert_allclose(x[0, :, :, 0].mean(), solid.mean())
+    y = U.make_input(solid, [[100.0, 0.5, 0.1]], 40)
+    assert set(np.unique(y[0, :, :, 0])) <= {0.0, 1.0}
+    np.testing.assert_allclose(y[0, ::2, ::2, 0], solid[0])
