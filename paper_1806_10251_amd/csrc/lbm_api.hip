@@ -40,7 +40,7 @@ namespace {
 struct Shape {
   int by, rows;
 };
-constexpr Shape kShapes[] = {{4, 1}, {8, 1}, {16, 1}, {4, 2}, {8, 2}, {4, 4}, {8, 4}};
+constexpr Shape kShapes[] = {{16, 1}, {8, 1}, {4, 1}, {4, 2}, {8, 2}, {4, 4}, {8, 4}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
 
@@ -61,12 +61,11 @@ struct lbm_ctx {
   void* hist[2] = {nullptr, nullptr};
   void* ubuf = nullptr;
   double* partials = nullptr;
-  uint8_t* d_fast = nullptr;   // per-tile interior flags
   double* result = nullptr;
   int cur = 0;
   int64_t t = 0;
   bool checked = false;
-  int by = 4, rows = 1;
+  int by = 16, rows = 1;
   int tiles_x = 0, tiles_y = 0, ntiles = 0, out_rows = 0;
   size_t partial_cap = 0;
   Consts<double> kd{};
@@ -98,18 +97,9 @@ int configure_tiles(lbm_ctx* c) {
   c->ntiles = c->tiles_x * c->tiles_y;
   if ((size_t)c->ntiles > c->partial_cap) {
     if (c->partials) HIPCHECK(hipFree(c->partials));
-    if (c->d_fast) HIPCHECK(hipFree(c->d_fast));
     c->partials = nullptr;
-    c->d_fast = nullptr;
     HIPCHECK(hipMalloc(&c->partials, (size_t)c->ntiles * 4 * sizeof(double)));
-    HIPCHECK(hipMalloc(&c->d_fast, (size_t)c->ntiles));
     c->partial_cap = c->ntiles;
-  }
-  {
-    const std::vector<uint8_t> f =
-        interior_tiles(c->grid.nx, c->grid.ny, c->h_solid.empty() ? nullptr : c->h_solid.data(),
-                       kLanes, c->tiles_x, c->tiles_y, c->out_rows);
-    HIPCHECK(hipMemcpy(c->d_fast, f.data(), f.size(), hipMemcpyHostToDevice));
   }
   for (int i = 0; i < 2; ++i)
     if (c->graph[i]) {
@@ -136,7 +126,6 @@ void enqueue_step(lbm_ctx* c, hipStream_t st) {
   a.hist_out = c->hist[c->cur ^ 1];
   a.ubuf = c->ubuf;
   a.partials = c->partials;
-  a.fast = c->d_fast;
   const void* src = c->lat[c->cur];
   void* dst = c->lat[c->cur ^ 1];
   switch (c->p.storage) {
@@ -238,7 +227,6 @@ void free_ctx(lbm_ctx* c) {
   if (c->d_solid) hipFree(c->d_solid);
   if (c->ubuf) hipFree(c->ubuf);
   if (c->partials) hipFree(c->partials);
-  if (c->d_fast) hipFree(c->d_fast);
   if (c->result) hipFree(c->result);
   if (c->ev0) hipEventDestroy(c->ev0);
   if (c->ev1) hipEventDestroy(c->ev1);
@@ -289,7 +277,7 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid_mask, const lbm_params
   c->kf = make_consts<float>(c->p, scale);
   c->esize = storage_bytes(c->p.storage);
   c->csize = c->p.storage == LBM_STORE_F64 ? 8 : 4;
-  c->by = 4;
+  c->by = 16;
   c->rows = 1;
   auto dev = [&](hipError_t e, const char* what) {
     if (e != hipSuccess) {

@@ -282,7 +282,6 @@ struct HostCase {
   int tiles_x = 0, ntiles = 0, tile_base = 0;
   size_t fluid = 0;
   int state_par = 0;  // which lattice holds the case's current state
-  std::vector<uint8_t> h_solid;  // host copy of the mask (interior-tile flags)
 };
 
 }  // namespace
@@ -313,7 +312,6 @@ struct lbm_batch {
   unsigned* d_sync = nullptr;  // [1 + n]: ticket counter, per-case completion counters
   int* d_err = nullptr;
   long long* d_tnow = nullptr; // step counter read by the reduction kernel
-  uint8_t* d_fast = nullptr;   // per-tile interior flags of all cases
   hipGraphExec_t graph[2] = {nullptr, nullptr};  // window graphs by start parity
   int64_t t = 0;
   std::vector<int> h_active;
@@ -345,7 +343,6 @@ void free_batch(lbm_batch* b) {
   hipFree(b->d_stall);
   hipFree(b->d_sync);
   hipFree(b->d_tnow);
-  hipFree(b->d_fast);
   for (int i = 0; i < 2; ++i)
     if (b->graph[i]) hipGraphExecDestroy(b->graph[i]);
   hipFree(b->d_err);
@@ -367,21 +364,6 @@ int configure(lbm_batch* b) {
   hipFree(b->d_partials);
   b->d_partials = nullptr;
   HIPCHECK(hipMalloc(&b->d_partials, (size_t)std::max(total, 1) * 4 * sizeof(double)));
-  {
-    std::vector<uint8_t> fast;
-    fast.reserve(total);
-    for (auto& c : b->cs) {
-      const std::vector<uint8_t> f =
-          interior_tiles(c.grid.nx, c.grid.ny, c.h_solid.data(), kLanes, c.tiles_x,
-                         c.ntiles / c.tiles_x, ro);
-      fast.insert(fast.end(), f.begin(), f.end());
-    }
-    hipFree(b->d_fast);
-    b->d_fast = nullptr;
-    HIPCHECK(hipMalloc(&b->d_fast, std::max<size_t>(fast.size(), 1)));
-    if (!fast.empty())
-      HIPCHECK(hipMemcpy(b->d_fast, fast.data(), fast.size(), hipMemcpyHostToDevice));
-  }
   std::vector<CaseDev> desc(b->n);
   for (int i = 0; i < b->n; ++i) {
     const HostCase& c = b->cs[i];
@@ -395,7 +377,6 @@ int configure(lbm_batch* b) {
       a.solid = c.solid;
       a.ubuf = c.ubuf;
       a.partials = b->d_partials + (long long)c.tile_base * 4;
-      a.fast = b->d_fast + c.tile_base;
       a.hist_in = c.hist[par];
       a.hist_out = c.hist[par ^ 1];
     }
@@ -638,7 +619,6 @@ int lbm_batch_create(int32_t n, const lbm_grid* grids, const uint8_t* const* mas
         solid += hm[q];
       }
     c.fluid = np - solid;
-    c.h_solid = hm;
     ok = ok && dev(hipMalloc(&c.solid, np), "hipMalloc mask") &&
          dev(hipMemcpy(c.solid, hm.data(), np, hipMemcpyHostToDevice), "copy mask");
   }

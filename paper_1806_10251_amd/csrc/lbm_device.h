@@ -299,33 +299,14 @@ __device__ __forceinline__ int collide(C d[9], C drx, C dry, const Consts<C>& k,
 // ---------------------------------------------------------------------------
 // Streaming (eq. 2b) as a pull through the ghost frame: nine independent loads.
 // ---------------------------------------------------------------------------
-// Address form: a wave-uniform base per direction (plane start shifted by
-// the source displacement, computed in scalar registers) plus one unsigned
-// 32-bit byte offset shared by the nine loads (the node's offset within a
-// plane), which maps onto the scalar-base + vector-offset global loads.
-template <class T>
-__device__ __forceinline__ const T* plane_src(const T* __restrict__ f, const Geom& g, int a) {
-  return f + ((long long)a * g.plane - ey_of(a) * g.pitch - ex_of(a));
-}
-
-template <class T>
-__device__ __forceinline__ const T& at_byte(const T* base, uint32_t off) {
-  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off);
-}
-
-template <class T>
-__device__ __forceinline__ T& at_byte(T* base, uint32_t off) {
-  return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off);
-}
-
 template <class S>
 __device__ __forceinline__ void pull9(const typename S::T* __restrict__ fa, const Geom& g,
                                       const Consts<typename S::C>& k, int x, int y,
                                       typename S::C d[9]) {
-  using T = typename S::T;
-  const uint32_t off = uint32_t(gidx(g, x, y)) * uint32_t(sizeof(T));
+  const int own = gidx(g, x, y);
 #pragma unroll
-  for (int a = 0; a < 9; ++a) d[a] = S::dec(at_byte(plane_src(fa, g, a), off), k.inv_scale);
+  for (int a = 0; a < 9; ++a)
+    d[a] = S::dec(fa[a * g.plane + own - ex_of(a) - ey_of(a) * g.pitch], k.inv_scale);
 }
 
 // Links of node (nx-1, y) that cross an OUTLET side (e_x = -1, source not a

@@ -5,7 +5,6 @@
 
 #include <cmath>
 #include <string>
-#include <vector>
 
 #include "../../include/lbm.h"
 #include "lbm_device.h"
@@ -81,39 +80,6 @@ inline Geom make_geom_for(int nx, int ny, const int32_t side[4], size_t esize) {
   g.pitch = ((nx + 2 * line) + line - 1) / line * line;
   g.plane = g.pitch * (ny + 2);
   return g;
-}
-
-// Per-tile flags for the interior path of the step kernel: 1 when the
-// tile's region (kLanes columns x ro rows of output nodes plus the one-node
-// ring around them) lies inside the lattice and holds no solid node.
-inline std::vector<uint8_t> interior_tiles(int nx, int ny, const uint8_t* solid, int lanes,
-                                           int tiles_x, int tiles_y, int ro) {
-  std::vector<uint8_t> f((size_t)tiles_x * tiles_y, 0);
-  // 2-D prefix sums of the mask for rectangle queries
-  std::vector<int64_t> ps;
-  if (solid) {
-    ps.assign((size_t)(nx + 1) * (ny + 1), 0);
-    for (int y = 0; y < ny; ++y)
-      for (int x = 0; x < nx; ++x)
-        ps[(size_t)(y + 1) * (nx + 1) + x + 1] = ps[(size_t)y * (nx + 1) + x + 1] +
-                                                 ps[(size_t)(y + 1) * (nx + 1) + x] -
-                                                 ps[(size_t)y * (nx + 1) + x] +
-                                                 (solid[(size_t)y * nx + x] != 0);
-  }
-  for (int ty = 0; ty < tiles_y; ++ty)
-    for (int tx = 0; tx < tiles_x; ++tx) {
-      const int x0 = tx * lanes - 1, x1 = tx * lanes + lanes;   // region columns x0..x1
-      const int y0 = ty * ro - 1, y1 = ty * ro + ro;            // region rows y0..y1
-      if (x0 < 0 || y0 < 0 || x1 > nx - 1 || y1 > ny - 1) continue;
-      if (solid) {
-        const int64_t n = ps[(size_t)(y1 + 1) * (nx + 1) + x1 + 1] -
-                          ps[(size_t)y0 * (nx + 1) + x1 + 1] -
-                          ps[(size_t)(y1 + 1) * (nx + 1) + x0] + ps[(size_t)y0 * (nx + 1) + x0];
-        if (n) continue;
-      }
-      f[(size_t)ty * tiles_x + tx] = 1;
-    }
-  return f;
 }
 
 // Validation shared by lbm_create and lbm_batch_create.

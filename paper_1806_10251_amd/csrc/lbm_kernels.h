@@ -52,7 +52,6 @@ struct StepArgs {
   void* hist_out;
   void* ubuf;             // [2][ny][nx] previous velocity (compute type)
   double* partials;       // [ntiles][4]
-  const uint8_t* fast;    // [ntiles]: 1 = interior tile without solid nodes
 };
 
 // Blocks are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8).
@@ -86,10 +85,8 @@ __device__ __forceinline__ void finish_node(typename S::T* __restrict__ fb, cons
                                             double acc[4]) {
   using C = typename S::C;
   const Geom& g = args.g;
-  using T = typename S::T;
-  const uint32_t off = uint32_t(li) * uint32_t(sizeof(T));
 #pragma unroll
-  for (int a = 0; a < 9; ++a) at_byte(fb + (long long)a * g.plane, off) = S::enc(d[a], k.scale);
+  for (int a = 0; a < 9; ++a) fb[a * g.plane + li] = S::enc(d[a], k.scale);
   C* ubuf = static_cast<C*>(args.ubuf);
   const int np = g.nx * g.ny;
   if (FL == kCheck) {
@@ -106,9 +103,8 @@ __device__ __forceinline__ void finish_node(typename S::T* __restrict__ fb, cons
   }
 }
 
-// Check-step partials of one block of NW wavefronts: wavefront shuffles,
-// then LDS.
-template <int NW>
+// Check-step partials of one block: wavefront shuffles, then LDS.
+template <int BY>
 __device__ __forceinline__ void block_partials(double acc[4], double (*s_red)[4], int lane, int w,
                                                double* __restrict__ out) {
 #pragma unroll
@@ -119,15 +115,16 @@ __device__ __forceinline__ void block_partials(double acc[4], double (*s_red)[4]
   __syncthreads();
   if (lane < 4 && w == 0) {
     double t = 0.0;
-    for (int i = 0; i < NW; ++i) t += s_red[i][lane];
+    for (int i = 0; i < BY; ++i) t += s_red[i][lane];
     out[lane] = t;
   }
 }
 
-// One tile of the fused step, any position (the general path).  LDS:
-// s_rho[(BY*R + 2) * 66] of type C, s_red[BY * 4].
+// One tile of the fused step (the body of both the single-lattice kernel and
+// the persistent batch kernel).  LDS: s_rho[(BY*R + 2) * 66] of type C,
+// s_red[BY * 4].
 template <class S, int BY, int R, int FL, bool OBST, bool OUTL>
-__device__ __forceinline__ void step_tile_general(const typename S::T* __restrict__ fa,
+__device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
                                           typename S::T* __restrict__ fb, const StepArgs& args,
                                           const Consts<typename S::C>& k, int tile,
                                           typename S::C (*s_rho)[kLanes + 2],
@@ -261,108 +258,6 @@ __device__ __forceinline__ void step_tile_general(const typename S::T* __restric
     }
   }
   if (FL == kCheck) block_partials<BY>(acc, s_red, lane, w, args.partials + (long long)tile * 4);
-}
-
-// Byte-offset pull (see pull9): the node's offset within a plane is given.
-template <class S>
-__device__ __forceinline__ void pull9_off(const typename S::T* __restrict__ fa, const Geom& g,
-                                          const Consts<typename S::C>& k, uint32_t off,
-                                          typename S::C d[9]) {
-#pragma unroll
-  for (int a = 0; a < 9; ++a) d[a] = S::dec(at_byte(plane_src(fa, g, a), off), k.inv_scale);
-}
-
-// A tile whose region (the output rows and the one-node ring around them)
-// lies inside the lattice and holds no solid node: every pull is a plain
-// neighbour load, every neighbour density is a fluid value and no link of
-// the tile's nodes crosses a side, so the boundary logic drops out.
-template <class S, int BY, int R, int FL>
-__device__ __forceinline__ void step_tile_interior(const typename S::T* __restrict__ fa,
-                                                   typename S::T* __restrict__ fb,
-                                                   const StepArgs& args,
-                                                   const Consts<typename S::C>& k, int tile,
-                                                   typename S::C (*s_rho)[kLanes + 2],
-                                                   double (*s_red)[4]) {
-  using C = typename S::C;
-  using T = typename S::T;
-  constexpr int RO = BY * R;
-  const Geom& g = args.g;
-  const int lane = threadIdx.x;
-  const int w = threadIdx.y;
-  const int x = (tile % args.tiles_x) * kLanes + lane;
-  const int ytile = (tile / args.tiles_x) * RO;
-  const int y0 = ytile + w * R;
-  const uint32_t esz = sizeof(T);
-  const uint32_t rowb = uint32_t(g.pitch) * esz;
-  const uint32_t off0 = uint32_t(gidx(g, x, y0)) * esz;
-  C d[R][9];
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    pull9_off<S>(fa, g, k, off0 + r * rowb, d[r]);
-    s_rho[w * R + r + 1][lane + 1] = sum9<C>(d[r]);
-  }
-  // halo columns: lanes 0 and 63 pull (x - 1) and (x + 1)
-  const bool halo_lane = lane == 0 || lane == kLanes - 1;
-  const int hc = lane == 0 ? 0 : kLanes + 1;
-  const uint32_t hoff = lane == 0 ? off0 - esz : off0 + esz;
-  if (halo_lane) {
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      C dh[9];
-      pull9_off<S>(fa, g, k, hoff + r * rowb, dh);
-      s_rho[w * R + r + 1][hc] = sum9<C>(dh);
-    }
-  }
-  if (w == 0 || w == BY - 1) {
-    // halo row above the tile (first wave) or below it (last wave)
-    const int lr = w == 0 ? 0 : RO + 1;
-    const uint32_t shift = w == 0 ? 0u - rowb : uint32_t(R) * rowb;
-    C dr[9];
-    pull9_off<S>(fa, g, k, off0 + shift, dr);
-    s_rho[lr][lane + 1] = sum9<C>(dr);
-    if (halo_lane) {
-      pull9_off<S>(fa, g, k, hoff + shift, dr);
-      s_rho[lr][hc] = sum9<C>(dr);
-    }
-  }
-  __syncthreads();
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int ry = w * R + r + 1;
-    const int c = lane + 1;
-    const C nE = s_rho[ry][c + 1], nW = s_rho[ry][c - 1];
-    const C nN = s_rho[ry + 1][c], nS = s_rho[ry - 1][c];
-    const C nNE = s_rho[ry + 1][c + 1], nNW = s_rho[ry + 1][c - 1];
-    const C nSE = s_rho[ry - 1][c + 1], nSW = s_rho[ry - 1][c - 1];
-    C drx, dry;
-    if (k.stencil == 0) {
-      drx = (nE - nW) * (C(1) / C(3)) + ((nNE - nNW) + (nSE - nSW)) * (C(1) / C(12));
-      dry = (nN - nS) * (C(1) / C(3)) + ((nNE - nSE) + (nNW - nSW)) * (C(1) / C(12));
-    } else {
-      drx = C(0.5) * (nE - nW);
-      dry = C(0.5) * (nN - nS);
-    }
-    C drho, ux, uy;
-    const int y = y0 + r;
-    const int gd = collide<C>(d[r], drx, dry, k, drho, ux, uy);
-    finish_node<S, FL>(fb, args, k, d[r], gidx(g, x, y), y * g.nx + x, drho, ux, uy, gd, acc);
-  }
-  if (FL == kCheck) block_partials<BY>(acc, s_red, lane, w, args.partials + (long long)tile * 4);
-}
-
-// One tile of the fused step (the body of both the single-lattice kernel and
-// the batch kernels): the interior path where the tile allows it.
-template <class S, int BY, int R, int FL, bool OBST, bool OUTL>
-__device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
-                                          typename S::T* __restrict__ fb, const StepArgs& args,
-                                          const Consts<typename S::C>& k, int tile,
-                                          typename S::C (*s_rho)[kLanes + 2],
-                                          double (*s_red)[4]) {
-  if (args.fast && args.fast[tile])
-    step_tile_interior<S, BY, R, FL>(fa, fb, args, k, tile, s_rho, s_red);
-  else
-    step_tile_general<S, BY, R, FL, OBST, OUTL>(fa, fb, args, k, tile, s_rho, s_red);
 }
 
 template <class S, int BY, int R, int FL, bool OBST, bool OUTL>
