@@ -65,7 +65,7 @@ struct lbm_ctx {
   int cur = 0;
   int64_t t = 0;
   bool checked = false;
-  int by = 16, rows = 1;
+  int by = 4, rows = 1;
   int tiles_x = 0, tiles_y = 0, ntiles = 0, out_rows = 0;
   size_t partial_cap = 0;
   Consts<double> kd{};
@@ -277,7 +277,7 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid_mask, const lbm_params
   c->kf = make_consts<float>(c->p, scale);
   c->esize = storage_bytes(c->p.storage);
   c->csize = c->p.storage == LBM_STORE_F64 ? 8 : 4;
-  c->by = 16;
+  c->by = 4;
   c->rows = 1;
   auto dev = [&](hipError_t e, const char* what) {
     if (e != hipSuccess) {

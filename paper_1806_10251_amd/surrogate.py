@@ -22,6 +22,7 @@ otherwise dominate the one-step residual.
 
 Command line (one GPU):
   python -m paper_1806_10251_amd.surrogate train --out weights.npy
+  python -m paper_1806_10251_amd.surrogate bench-train   (training-step timing)
 """
 from __future__ import annotations
 
@@ -207,6 +208,47 @@ def warm_init(net, cases):
     return init
 
 
+# (cin, cout, level) of the 15 convolutions, in network order
+CONVS = [(32, 32, 0), (32, 32, 0), (32, 64, 1), (64, 64, 1), (64, 128, 2), (128, 128, 2),
+         (128, 256, 3), (256, 256, 3), (384, 128, 2), (128, 128, 2), (192, 64, 1), (64, 64, 1),
+         (96, 32, 0), (32, 32, 0), (32, 32, 0)]
+
+
+def network_flops(res, batch=1):
+    """(forward, training step) FLOPs of the convolutions: 2 * 9 * cin * cout
+    per output pixel; a training step adds the input gradient (all layers
+    but the first) and the weight gradient."""
+    fwd = sum(2 * 9 * ci * co * (res >> lv) ** 2 for ci, co, lv in CONVS)
+    first = 2 * 9 * 32 * 32 * res * res
+    return batch * fwd, batch * (3 * fwd - first)
+
+
+def bench_train(steps=50, batch=16, seed=0):
+    """Time training steps on synthetic inputs (random geometry, smooth
+    targets): returns (ms per step, TFLOP/s of the convolutions)."""
+    import torch
+    rng = np.random.default_rng(seed)
+    solid = torch.tensor((rng.random((batch, RES, RES)) > 0.9).astype(np.uint8), device="cuda")
+    cp = torch.tensor(np.tile([[200.0, 0.5, 0.1]], (batch, 1)).astype(np.float32), device="cuda")
+    x0 = U.make_input(solid, cp, RES)
+    c = (np.arange(RES) + 0.5) / RES
+    X, Y = np.meshgrid(c, c)
+    t = np.stack([np.sin(2 * np.pi * X), X * Y, Y - 0.5], axis=-1)
+    t = torch.tensor(np.broadcast_to(t, (batch, RES, RES, 3)).astype(np.float32), device="cuda")
+    fluid = (1 - solid).contiguous()
+    net = U.UNet(max_batch=batch, res=RES, seed=seed)
+    for _ in range(3):
+        net.train_step(x0, t, fluid, 1e-4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        net.train_step(x0, t, fluid, 1e-4)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    net.close()
+    return ms, network_flops(RES, batch)[1] / (ms * 1e-3) / 1e12
+
+
 def save(net, path):
     np.save(path, net.params())
 
@@ -231,7 +273,20 @@ def main(argv=None):
     t.add_argument("--max-steps", type=int, default=300000)
     t.add_argument("--out", required=True)
     t.add_argument("--data-cache", default="")
+    bt = sub.add_parser("bench-train")
+    bt.add_argument("--steps", type=int, default=50)
+    bt.add_argument("--batch", type=int, default=16)
     args = ap.parse_args(argv)
+    if args.cmd == "bench-train":
+        import torch
+        if not torch.cuda.is_available():
+            sys.exit("needs a GPU")
+        L.load()
+        U.load()
+        ms, tf = bench_train(args.steps, args.batch)
+        print(f"[surrogate] training step (batch {args.batch}, {RES}x{RES}): {ms:.2f} ms, "
+              f"{tf:.1f} TFLOP/s in the convolutions", flush=True)
+        return
 
     import torch
     if not torch.cuda.is_available():
