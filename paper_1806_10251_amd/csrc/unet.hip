@@ -184,6 +184,7 @@ struct WgradArgs {
 };
 
 constexpr int kPadPx = 40;   // LDS row length (32 pixels + 8) in bf16
+constexpr int kWgrad2Blocks = 1024;   // blocks the channel-major path aims for
 
 __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a) {
   __shared__ bf16 sA[4][32][kPadPx];   // per wave: dy tile [co][pixel]
@@ -260,6 +261,159 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a) {
   }
 }
 
+// ---- weight gradient on channel-major copies (width a multiple of 8) ------
+// The pixel sum is the MFMA reduction dimension, so both operands are first
+// copied channel-major ([c][p], pixels contiguous): then every A and B
+// operand is 8 consecutive pixels of one channel, one 16-byte load (two and
+// a lane-local shift for the taps with dx = +-1), with no LDS transposes.
+
+// dst[c * rowlen + p] = src[p][c] for c < ch, p < npix (bf16; rowlen a
+// multiple of 8); 64 pixels x 32 channels per block through LDS.
+__global__ __launch_bounds__(256) void to_channel_major_kernel(const bf16* __restrict__ src,
+                                                                int lds, bf16* __restrict__ dst,
+                                                                int npix, int rowlen) {
+  __shared__ bf16 t[64][32 + 2];
+  const int p0 = blockIdx.x * 64, c0 = blockIdx.y * 32;
+  // load: 64 pixels x 4 vectors of 8 channels = 256 vectors, one per thread
+  {
+    const int pl = threadIdx.x >> 2, cv = threadIdx.x & 3;
+    const int p = p0 + pl;
+    bf16x8 v = bf16x8{};
+    if (p < npix) v = *reinterpret_cast<const bf16x8*>(src + (long long)p * lds + c0 + 8 * cv);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[pl][8 * cv + u] = v[u];
+  }
+  __syncthreads();
+  // store: 32 channels x 8 vectors of 8 pixels = 256 vectors
+  {
+    const int c = threadIdx.x >> 3, pv = threadIdx.x & 7;
+    const int p = p0 + 8 * pv;
+    if (p < npix) {
+      bf16x8 o;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) o[u] = t[8 * pv + u][c];
+      if (p + 8 <= npix) {
+        *reinterpret_cast<bf16x8*>(dst + (long long)(c0 + c) * rowlen + p) = o;
+      } else {
+        for (int u = 0; u < 8 && p + u < npix; ++u) dst[(long long)(c0 + c) * rowlen + p + u] = o[u];
+      }
+    }
+  }
+}
+
+struct Wgrad2Args {
+  const bf16* dyT;    // [cout][npix]
+  const bf16* xT;     // [cin][npix]
+  float* part;        // [splits][cout][9][cin]
+  int npix, npad, h, wd, cin, cout, chunk;
+};
+
+// 8 consecutive pixels p .. p + 7 (one row: p % 8 == 0, width % 8 == 0) of
+// channel row `row` (npad elements, a multiple of 8), shifted by the tap
+// (dy, dx) with zero padding.
+__device__ __forceinline__ bf16x8 tap_row8(const bf16* __restrict__ row, int p, int npix,
+                                           int npad, int h, int wd, int dy, int dx) {
+  bf16x8 z = bf16x8{};
+  if (p >= npix) return z;
+  const int y = (p / wd) % h;
+  if (y + dy < 0 || y + dy >= h) return z;
+  const int q = p + dy * wd;   // aligned source of the unshifted columns
+  const bf16x8 v0 = *reinterpret_cast<const bf16x8*>(row + q);
+  if (dx == 0) return v0;
+  bf16x8 o;
+  if (dx < 0) {
+    // pixel p + u takes column u - 1: the element before the vector, zero
+    // at the start of a row
+    const bool first = p % wd == 0;
+    const bf16x8 vp = *reinterpret_cast<const bf16x8*>(row + (q >= 8 ? q - 8 : 0));
+    o[0] = first ? bf16(0.f) : vp[7];
+#pragma unroll
+    for (int u = 1; u < 8; ++u) o[u] = v0[u - 1];
+  } else {
+    const bool last = (p + 8) % wd == 0;
+    const bf16x8 vn = *reinterpret_cast<const bf16x8*>(row + (q + 8 < npad ? q + 8 : q));
+#pragma unroll
+    for (int u = 0; u < 7; ++u) o[u] = v0[u + 1];
+    o[7] = last ? bf16(0.f) : vn[0];
+  }
+  return o;
+}
+
+__global__ __launch_bounds__(256) void wgrad2_kernel(Wgrad2Args a) {
+  __shared__ float sR[4][32][33];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int bid = blockIdx.x;
+  const int t = bid % 9;
+  bid /= 9;
+  const int nci = a.cin / 32;
+  const int ci0 = (bid % nci) * 32, co0 = (bid / nci) * 32;
+  const int dy = t / 3 - 1, dx = t % 3 - 1;
+  const int pbeg = blockIdx.y * a.chunk;
+  const int r = lane & 15, g = lane >> 4;
+  const bf16* arow[2];
+  const bf16* brow[2];
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    arow[b] = a.dyT + (long long)(co0 + 16 * b + r) * a.npad;
+    brow[b] = a.xT + (long long)(ci0 + 16 * b + r) * a.npad;
+  }
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = pbeg + 32 * wv; k0 < pbeg + a.chunk; k0 += 128) {
+    const int p = k0 + 8 * g;
+    bf16x8 A[2], B[2];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      A[b] = p < a.npix ? *reinterpret_cast<const bf16x8*>(arow[b] + p) : bf16x8{};
+      B[b] = tap_row8(brow[b], p, a.npix, a.npad, a.h, a.wd, dy, dx);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = mfma16(A[i], B[j], acc[i][j]);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sR[wv][16 * i + 4 * g + v][16 * j + r] = acc[i][j][v];
+  __syncthreads();
+  for (int e = threadIdx.x; e < 1024; e += 256) {
+    const int co = e >> 5, ci = e & 31;
+    const float s = sR[0][co][ci] + sR[1][co][ci] + sR[2][co][ci] + sR[3][co][ci];
+    a.part[(((long long)blockIdx.y * a.cout + co0 + co) * 9 + t) * a.cin + ci0 + ci] = s;
+  }
+}
+
+// bias partials: bpart[s][co] = sum of dy over the pixels of split s; one
+// block per (channel, split), 8 pixels per load, fixed-order tree in LDS
+__global__ __launch_bounds__(256) void bias_partial_kernel(const bf16* __restrict__ dyT, int npad,
+                                                           int npix, int chunk, int cout,
+                                                           float* __restrict__ bpart) {
+  __shared__ float sm[256];
+  const int co = blockIdx.x;
+  const int pbeg = blockIdx.y * chunk, pend = min(npix, pbeg + chunk);
+  const bf16* row = dyT + (long long)co * npad;
+  float s = 0.f;
+  for (int p = pbeg + 8 * (int)threadIdx.x; p < pend; p += 8 * 256) {
+    const bf16x8 v = *reinterpret_cast<const bf16x8*>(row + p);
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (p + u < pend) s += (float)v[u];
+  }
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bpart[(long long)blockIdx.y * cout + co] = sm[0];
+}
+
 // out[i] = sum_s part[s][i] (fixed order)
 __global__ void sum_splits_kernel(const float* part, long long count, int splits, float* out) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count;
@@ -270,9 +424,9 @@ __global__ void sum_splits_kernel(const float* part, long long count, int splits
   }
 }
 
-void wgrad_plan(int npix, int cin, int cout, int* splits, int* chunk) {
+void wgrad_plan(int npix, int cin, int cout, int* splits, int* chunk, int target = 2048) {
   const int base = (cout / 32) * (cin / 32) * 9;
-  const int want = std::max(1, (2048 + base - 1) / base);
+  const int want = std::max(1, (target + base - 1) / base);
   int c = (npix + want - 1) / want;
   c = std::max(128, (c + 127) / 128 * 128);
   *chunk = c;
@@ -431,15 +585,28 @@ __global__ __launch_bounds__(256) void loss_partial_kernel(const float* out, int
   }
 }
 
-__global__ void loss_final_kernel(double* work, int blocks) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// fixed-order tree over the per-block partials (one block of 256 threads)
+__global__ __launch_bounds__(256) void loss_final_kernel(double* work, int blocks) {
+  __shared__ double ssq[256], sn[256];
   double sq = 0.0, n = 0.0;
-  for (int b = 0; b < blocks; ++b) {
+  for (int b = threadIdx.x; b < blocks; b += 256) {
     sq += work[2 * b];
     n += work[2 * b + 1];
   }
-  work[2 * blocks] = n > 0 ? sq / (3.0 * n) : 0.0;
-  work[2 * blocks + 1] = n;
+  ssq[threadIdx.x] = sq;
+  sn[threadIdx.x] = n;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      ssq[threadIdx.x] += ssq[threadIdx.x + w];
+      sn[threadIdx.x] += sn[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    work[2 * blocks] = sn[0] > 0 ? ssq[0] / (3.0 * sn[0]) : 0.0;
+    work[2 * blocks + 1] = sn[0];
+  }
 }
 
 __global__ void loss_grad_kernel(const float* out, int ldo, const float* t, const uint8_t* fluid,
@@ -654,7 +821,15 @@ int64_t unet_wgrad_work_floats(int32_t n, int32_t h, int32_t wd, int32_t cin, in
   if (n <= 0 || h <= 0 || wd <= 0 || cin <= 0 || cout <= 0) return 0;
   int splits, chunk;
   wgrad_plan(n * h * wd, cin, cout, &splits, &chunk);
-  return (int64_t)splits * (9LL * cin * cout + cout);
+  int64_t words = (int64_t)splits * (9LL * cin * cout + cout);
+  if (wd % 8 == 0) {
+    // channel-major path: fewer splits, plus the two bf16 copies
+    wgrad_plan(n * h * wd, cin, cout, &splits, &chunk, kWgrad2Blocks);
+    const int64_t npad = ((int64_t)n * h * wd + 7) / 8 * 8 + 8;
+    words = std::max<int64_t>(words, (int64_t)splits * (9LL * cin * cout + cout) +
+                                         (npad * (cin + cout) + 1) / 2 + 64);
+  }
+  return words;
 }
 
 int unet_conv3x3_bwd_weight(const void* dy, int32_t lddy, const void* x, int32_t ldx, float* dw,
@@ -669,8 +844,37 @@ int unet_conv3x3_bwd_weight(const void* dy, int32_t lddy, const void* x, int32_t
   hipStream_t st = as_stream(stream);
   const int npix = n * h * wd;
   int splits, chunk;
-  wgrad_plan(npix, cin, cout, &splits, &chunk);
   const long long wcount = 9LL * cin * cout;
+  if (wd % 8 == 0) {
+    wgrad_plan(npix, cin, cout, &splits, &chunk, kWgrad2Blocks);
+    const int npad = (npix + 7) / 8 * 8 + 8;
+    float* part = work;
+    float* bpart = work + (long long)splits * wcount;
+    // bf16 copies after the partial sums (256-byte aligned)
+    const long long used = ((long long)splits * (wcount + cout) + 63) / 64 * 64;
+    bf16* dyT = reinterpret_cast<bf16*>(work + used);
+    bf16* xT = dyT + (long long)cout * npad;
+    hipLaunchKernelGGL(to_channel_major_kernel, dim3((npix + 63) / 64, cout / 32), dim3(256), 0,
+                       st, static_cast<const bf16*>(dy), lddy, dyT, npix, npad);
+    hipLaunchKernelGGL(to_channel_major_kernel, dim3((npix + 63) / 64, cin / 32), dim3(256), 0,
+                       st, static_cast<const bf16*>(x), ldx, xT, npix, npad);
+    UCHECK(hipGetLastError());
+    Wgrad2Args a2{dyT, xT, part, npix, npad, h, wd, cin, cout, chunk};
+    hipLaunchKernelGGL(wgrad2_kernel, dim3((cout / 32) * (cin / 32) * 9, splits), dim3(256), 0,
+                       st, a2);
+    if (dbias)
+      hipLaunchKernelGGL(bias_partial_kernel, dim3(cout, splits), dim3(256), 0, st, dyT, npad,
+                         npix, chunk, cout, bpart);
+    UCHECK(hipGetLastError());
+    hipLaunchKernelGGL(sum_splits_kernel, dim3(grid_for(wcount)), dim3(256), 0, st, part, wcount,
+                       splits, dw);
+    if (dbias)
+      hipLaunchKernelGGL(sum_splits_kernel, dim3(grid_for(cout)), dim3(256), 0, st, bpart,
+                         (long long)cout, splits, dbias);
+    UCHECK(hipGetLastError());
+    return UNET_OK;
+  }
+  wgrad_plan(npix, cin, cout, &splits, &chunk);
   WgradArgs a{static_cast<const bf16*>(dy), lddy, static_cast<const bf16*>(x), ldx, work,
               work + (long long)splits * wcount, npix, h, wd, cin, cout, chunk};
   dim3 grid((cout / 32) * (cin / 32) * 9, splits);
@@ -757,7 +961,7 @@ int unet_mse_loss(const float* out, int32_t ldo, const float* target, const uint
   hipStream_t st = as_stream(stream);
   hipLaunchKernelGGL(loss_partial_kernel, dim3(kLossBlocks), dim3(256), 0, st, out, ldo, target,
                      fluid, (long long)npix, work);
-  hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(64), 0, st, work, kLossBlocks);
+  hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(256), 0, st, work, kLossBlocks);
   hipLaunchKernelGGL(loss_grad_kernel, dim3(grid_for(npix * ldo)), dim3(256), 0, st, out, ldo,
                      target, fluid, (long long)npix, static_cast<bf16*>(dout),
                      (const double*)(work + 2 * kLossBlocks));

@@ -84,9 +84,11 @@ def test_conv_backward_data(U, n, h, w, cin, cout):
 
 
 @pytest.mark.parametrize("n,h,w,cin,cout", [
-    (2, 12, 20, 64, 32),     # pixel count not a multiple of the split size
-    (4, 64, 64, 32, 32),     # many splits
-    (2, 8, 8, 256, 256),     # bottom level
+    (2, 12, 20, 64, 32),     # width not a multiple of 8: LDS-transpose path
+    (4, 64, 64, 32, 32),     # channel-major path, many splits
+    (2, 8, 8, 256, 256),     # bottom level: every vector ends a row
+    (3, 5, 24, 64, 32),      # pixel count not a multiple of 32
+    (2, 16, 8, 96, 64),      # concatenated input width
 ])
 def test_conv_backward_weight(U, n, h, w, cin, cout):
     import torch
