@@ -100,7 +100,10 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid_mask, const lbm_params
 int lbm_init_fields(lbm_ctx* ctx, const double* rho, const double* ux, const double* uy);
 
 /* Same, from device arrays of ny*nx floats (e.g. a warm-start prediction
- * already on the GPU).  NULL -> rho0 / zero velocity. */
+ * already on the GPU).  NULL -> rho0 / zero velocity.  Asynchronous on the
+ * context's stream: the arrays must be complete with respect to that stream
+ * (synchronise the stream that wrote them, or share it via
+ * lbm_set_stream). */
 int lbm_init_fields_device(lbm_ctx* ctx, const float* rho, const float* ux, const float* uy);
 
 /* Queue all further work on hip_stream (a hipStream_t; NULL = the context's
@@ -141,7 +144,7 @@ int lbm_steps(lbm_ctx* ctx, int64_t* n);
  * ny*nx doubles (any may be NULL).  Solid nodes report 0.  Synchronises. */
 int lbm_fields(lbm_ctx* ctx, double* rho, double* ux, double* uy);
 
-/* Same into device arrays of ny*nx floats (asynchronous). */
+/* Same into device arrays of ny*nx floats.  Synchronises. */
 int lbm_fields_device(lbm_ctx* ctx, float* rho, float* ux, float* uy);
 
 /* Current post-collision populations f (not deviations), decoded to FP64,

@@ -510,7 +510,10 @@ int lbm_fields(lbm_ctx* c, double* rho, double* ux, double* uy) {
 
 int lbm_fields_device(lbm_ctx* c, float* rho, float* ux, float* uy) {
   if (!c) return fail(LBM_EINVAL, "null context");
-  return export_common(c, nullptr, rho, ux, uy, nullptr, nullptr, nullptr);
+  const int rc = export_common(c, nullptr, rho, ux, uy, nullptr, nullptr, nullptr);
+  if (rc) return rc;
+  HIPCHECK(hipStreamSynchronize(c->stream));
+  return LBM_OK;
 }
 
 int lbm_populations(lbm_ctx* c, double* f) {

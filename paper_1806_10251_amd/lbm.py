@@ -168,6 +168,14 @@ def launch_shapes():
     return [(buf[2 * i], buf[2 * i + 1]) for i in range(n)]
 
 
+def _ready(*tensors):
+    """Wait for the current torch stream when device tensors are passed:
+    they may still be being written there."""
+    if any(t is not None and hasattr(t, "data_ptr") for t in tensors):
+        import torch
+        torch.cuda.current_stream().synchronize()
+
+
 class Lattice:
     """One lattice on the current HIP device (wraps lbm_ctx)."""
 
@@ -206,6 +214,9 @@ class Lattice:
         _check(load().lbm_init_fields(self._h, *[p for _, p in arrs]))
 
     def init_fields_device(self, rho=None, ux=None, uy=None):
+        """Device float32 tensors; the library reads them on its own stream,
+        so the producing (current torch) stream is synchronised first."""
+        _ready(rho, ux, uy)
         _check(load().lbm_init_fields_device(self._h, _dev_ptr(rho), _dev_ptr(ux), _dev_ptr(uy)))
 
     def set_stream(self, stream):
@@ -246,6 +257,7 @@ class Lattice:
         return tuple(out)
 
     def fields_device(self, rho=None, ux=None, uy=None):
+        """Write the fields into device float32 tensors (synchronises)."""
         _check(load().lbm_fields_device(self._h, _dev_ptr(rho), _dev_ptr(ux), _dev_ptr(uy)))
 
     def populations(self):
@@ -318,6 +330,8 @@ class Batch:
         _check(load().lbm_batch_init_fields(self._h, int(c), *[p for _, p in arrs]))
 
     def init_fields_device(self, c, rho=None, ux=None, uy=None):
+        """As Lattice.init_fields_device, for case c."""
+        _ready(rho, ux, uy)
         _check(load().lbm_batch_init_fields_device(self._h, int(c), _dev_ptr(rho), _dev_ptr(ux),
                                                    _dev_ptr(uy)))
 

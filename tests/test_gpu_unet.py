@@ -215,3 +215,31 @@ def test_training_reduces_the_loss(U):
     _say("loss", first, "->", last)
     assert last < 0.6 * first
     net.close()
+
+
+def test_warm_start_initialises_the_predicted_fields(U):
+    """The lattice starts from exactly the fields the network predicted:
+    predictions are written on torch's stream and read by the library on its
+    own, so the hand-over must wait for them (a missing wait left some cases
+    initialised from partly written fields)."""
+    import torch
+    from paper_1806_10251_amd import lbm as L
+    from paper_1806_10251_amd import surrogate as S
+    cases = S.cavity_cases(6, 99, 64)
+    net = U.UNet(max_batch=8, res=S.RES, seed=3)
+    grids = [L.make_grid(k.nx, k.ny, k.sides) for k in cases]
+    params = [L.make_params(storage="f64", check_every=100, nu=k.nu, gamma=k.gamma,
+                            u_lid=k.u_ref) for k in cases]
+    for _ in range(3):
+        b = L.Batch(grids, [k.mask for k in cases], params)
+        pred = S.predict_fields(net, cases)
+        S.warm_init(net, cases)(0, len(cases), b)
+        for i, k in enumerate(cases):
+            r, ux, uy = b.fields(i, k.ny, k.nx)
+            fl = k.mask == 0
+            pr, pu, pv = (t.float().cpu().numpy().astype(np.float64) for t in pred[i])
+            assert np.abs(ux - pu)[fl].max() < 1e-6 * max(1.0, np.abs(pu).max())
+            assert np.abs(uy - pv)[fl].max() < 1e-6 * max(1.0, np.abs(pv).max())
+            assert np.abs(r - pr)[fl].max() < 1e-6
+        b.close()
+    net.close()
