@@ -139,6 +139,94 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(ConvArgs a) {
     }
 }
 
+// Larger wave tiles for large layers: v_mfma_f32_32x32x16_bf16 (lane l
+// holds A[l % 32][8 (l / 32) + v], B[8 (l / 32) + v][l % 32] for v < 8 and
+// D[8 (v / 4) + 4 (l / 32) + v % 4][l % 32] for v < 16; verified on the
+// device).  A wave owns 64 pixels x (32 CT) output channels: per step of 16
+// input channels it loads two pixel operands and CT weight operands and
+// issues 2 CT MFMAs, twice the work per loaded byte of the 16x16x32 tiling.
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kConv32MinPix = 65536;  // layers with at least this many pixels
+                                      // use the 64-pixel wave tiles
+
+__device__ __forceinline__ f32x16 mfma32(const bf16x8& a, const bf16x8& b, const f32x16& c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+template <int CT>
+__global__ __launch_bounds__(256) void conv_fwd32_kernel(ConvArgs a) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int px0 = blockIdx.x * 256 + 64 * wv;
+  const int co0 = blockIdx.y * (32 * CT);
+  const int r = lane & 31, g = lane >> 5;
+  int pidx[2], py[2], pxx[2];
+  bool pv[2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const int p = px0 + 32 * s + r;
+    pv[s] = p < a.npix;
+    const int q = pv[s] ? p : 0;
+    pidx[s] = q;
+    pxx[s] = q % a.wd;
+    py[s] = (q / a.wd) % a.h;
+  }
+  f32x16 acc[2][CT];
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int b = 0; b < CT; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[s][b][v] = 0.f;
+  for (int t = 0; t < 9; ++t) {
+    const int dy = t / 3 - 1, dx = t % 3 - 1;
+    const bf16* xa[2];
+    bool ok[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int yy = py[s] + dy, xx = pxx[s] + dx;
+      ok[s] = pv[s] && yy >= 0 && yy < a.h && xx >= 0 && xx < a.wd;
+      xa[s] = a.x + (long long)(ok[s] ? pidx[s] + dy * a.wd + dx : 0) * a.ldx + 8 * g;
+    }
+    const bf16* wb[CT];
+#pragma unroll
+    for (int b = 0; b < CT; ++b)
+      wb[b] = a.w + ((long long)(co0 + 32 * b + r) * 9 + t) * a.cin + 8 * g;
+    for (int c0 = 0; c0 < a.cin; c0 += 16) {
+      bf16x8 A[2], B[CT];
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        A[s] = *reinterpret_cast<const bf16x8*>(xa[s] + c0);
+        if (!ok[s]) A[s] = bf16x8{};
+      }
+#pragma unroll
+      for (int b = 0; b < CT; ++b) B[b] = *reinterpret_cast<const bf16x8*>(wb[b] + c0);
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int b = 0; b < CT; ++b) acc[s][b] = mfma32(A[s], B[b], acc[s][b]);
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int b = 0; b < CT; ++b) {
+      const int co = co0 + 32 * b + r;
+      const float bias = a.bias ? a.bias[co] : 0.f;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int p = px0 + 32 * s + 8 * (v / 4) + 4 * g + (v % 4);
+        if (p >= a.npix) continue;
+        float val = acc[s][b][v] + bias;
+        if (a.relu) val = fmaxf(val, 0.f);
+        if (a.out_f32)
+          static_cast<float*>(a.y)[(long long)p * a.ldy + co] = val;
+        else
+          static_cast<bf16*>(a.y)[(long long)p * a.ldy + co] = (bf16)val;
+      }
+    }
+}
+
 int launch_conv(const ConvArgs& a, hipStream_t st) {
   if (a.cin <= 0 || a.cout <= 0 || a.cin % 32 || a.cout % 32)
     return fail(UNET_EINVAL, "conv: cin and cout must be positive multiples of 32");
@@ -147,7 +235,16 @@ int launch_conv(const ConvArgs& a, hipStream_t st) {
   if (a.npix <= 0 || a.h <= 0 || a.wd <= 0 || a.npix % (a.h * a.wd))
     return fail(UNET_EINVAL, "conv: bad image size");
   if (!a.x || !a.w || !a.y) return fail(UNET_EINVAL, "conv: null pointer");
-  if (a.cout % 64 == 0) {
+  if (a.npix >= kConv32MinPix) {
+    // large layers: 64-pixel wave tiles on the 32x32x16 MFMA
+    if (a.cout % 64 == 0) {
+      dim3 grid((a.npix + 255) / 256, a.cout / 64);
+      hipLaunchKernelGGL(conv_fwd32_kernel<2>, grid, dim3(256), 0, st, a);
+    } else {
+      dim3 grid((a.npix + 255) / 256, a.cout / 32);
+      hipLaunchKernelGGL(conv_fwd32_kernel<1>, grid, dim3(256), 0, st, a);
+    }
+  } else if (a.cout % 64 == 0) {
     dim3 grid((a.npix + 63) / 64, a.cout / 64);
     hipLaunchKernelGGL(conv_fwd_kernel<2>, grid, dim3(256), 0, st, a);
   } else {

@@ -48,6 +48,8 @@ def bf(rng, *shape, scale=1.0):
     (2, 12, 20, 64, 96, 0),      # ragged pixel count, 32-channel output tiles
     (1, 16, 16, 32, 64, 32),     # 64-channel output tiles, input with ld > cin
     (3, 8, 8, 384, 128, 0),      # concatenated input width of the decoder
+    (1, 256, 256, 32, 32, 0),    # large layer: 64-pixel wave tiles, 32 channels
+    (1, 253, 260, 64, 64, 32),   # large and ragged (partial last block), ld > cin
 ])
 def test_conv_forward(U, n, h, w, cin, cout, ld_extra):
     import torch
@@ -69,7 +71,8 @@ def test_conv_forward(U, n, h, w, cin, cout, ld_extra):
     assert (err <= 2 ** -8 * np.abs(refr) + 1e-5 * bound + 1e-6).all(), err.max()
 
 
-@pytest.mark.parametrize("n,h,w,cin,cout", [(2, 12, 20, 64, 32), (1, 16, 16, 128, 256)])
+@pytest.mark.parametrize("n,h,w,cin,cout", [(2, 12, 20, 64, 32), (1, 16, 16, 128, 256),
+                                            (1, 256, 260, 32, 64)])
 def test_conv_backward_data(U, n, h, w, cin, cout):
     import torch
     _say("conv bwd data", n, h, w, cin, cout)
