@@ -78,6 +78,8 @@ def lib():
         L.orc_fields.argtypes = [ctypes.c_void_p, dp, dp, dp]
         L.orc_get_f.argtypes = [ctypes.c_void_p, dp]
         L.orc_set_f.argtypes = [ctypes.c_void_p, dp]
+        L.orc_set_force_field.argtypes = [ctypes.c_void_p, dp, dp]
+        L.orc_set_force_field.restype = ctypes.c_int
         L.orc_raw_moments.argtypes = [dp, dp]
         L.orc_moments_to_pop.argtypes = [dp, dp]
         L.orc_equilibrium.argtypes = [ctypes.c_double] * 4 + [dp]
@@ -183,6 +185,17 @@ class Oracle:
         f = np.ascontiguousarray(f, dtype=np.float64)
         assert f.shape == (9, self.ny, self.nx)
         lib().orc_set_f(self._h, _dp(f))
+
+    def set_force_field(self, fx, fy):
+        """Per-node body force [ny][nx] (None, None: the uniform force)."""
+        if fx is None and fy is None:
+            rc = lib().orc_set_force_field(self._h, None, None)
+        else:
+            self._ffx = np.ascontiguousarray(fx, dtype=np.float64).reshape(self.ny, self.nx)
+            self._ffy = np.ascontiguousarray(fy, dtype=np.float64).reshape(self.ny, self.nx)
+            rc = lib().orc_set_force_field(self._h, _dp(self._ffx), _dp(self._ffy))
+        if rc:
+            raise ValueError("bad force field")
 
 
 # --- single-node entry points (unit-level pins) -----------------------------

@@ -114,11 +114,14 @@ typedef struct {
   double *drx, *dry;        /* density gradient */
   double *hist;   /* outlet history: [2][ny] velocity u* of the last column */
   double *hist_next;
+  double *ffx, *ffy; /* per-node body force [ny][nx] (NULL: the uniform p.fx, p.fy) */
   double resid, mass;
   int64_t steps, guards;
 } orc;
 
 #define IDX(o, i, j) ((size_t)(j) * (o)->nx + (i))
+#define FXN(o, k) ((o)->ffx ? (o)->ffx[k] : (o)->p.fx)
+#define FYN(o, k) ((o)->ffy ? (o)->ffy[k] : (o)->p.fy)
 #define FQ(o, arr, a, i, j) ((arr)[(size_t)(a) * (o)->nx * (o)->ny + IDX(o, i, j)])
 
 /* ------------------------------------------------------------------ */
@@ -392,8 +395,8 @@ static void outlet_links(orc *o, int j) {
   for (int a = 0; a < 9; ++a) f2[a] = pull(o, nx - 2, j, a, NULL);
   orc_raw_moments(f2, m2);
   double r2 = m2[0];
-  double u2 = (m2[1] + 0.5 * o->p.fx / o->p.gamma) / r2;
-  double v2 = (m2[2] + 0.5 * o->p.fy / o->p.gamma) / r2;
+  double u2 = (m2[1] + 0.5 * FXN(o, IDX(o, nx - 2, j)) / o->p.gamma) / r2;
+  double v2 = (m2[2] + 0.5 * FYN(o, IDX(o, nx - 2, j)) / o->p.gamma) / r2;
   double U = o->p.u_in_max;
   double us = (o->hist[0 * ny + j] + U * u2) / (1.0 + U);
   double vs = (o->hist[1 * ny + j] + U * v2) / (1.0 + U);
@@ -493,8 +496,33 @@ orc *orc_create(int nx, int ny, const int32_t side[4], const uint8_t *solid,
   return o;
 }
 
+/* Per-node body force F(x, y) (copied; NULL, NULL returns to the uniform
+ * force of the parameters).  Enters every place the uniform force does:
+ * rho u = sum e fbar + F/(2 gamma) and the source moments of Sec. 2.
+ * Returns 0, or -1 when only one component is given or memory runs out. */
+int orc_set_force_field(orc *o, const double *fx, const double *fy) {
+  if (!o || (!fx) != (!fy)) return -1;
+  free(o->ffx);
+  free(o->ffy);
+  o->ffx = o->ffy = NULL;
+  if (!fx) return 0;
+  size_t n = (size_t)o->nx * o->ny;
+  o->ffx = (double *)malloc(n * sizeof(double));
+  o->ffy = (double *)malloc(n * sizeof(double));
+  if (!o->ffx || !o->ffy) {
+    free(o->ffx);
+    free(o->ffy);
+    o->ffx = o->ffy = NULL;
+    return -1;
+  }
+  memcpy(o->ffx, fx, n * sizeof(double));
+  memcpy(o->ffy, fy, n * sizeof(double));
+  return 0;
+}
+
 void orc_destroy(orc *o) {
   if (!o) return;
+  free(o->ffx); free(o->ffy);
   free(o->solid); free(o->f); free(o->fb); free(o->rho); free(o->ux); free(o->uy);
   free(o->uxp); free(o->uyp); free(o->drx); free(o->dry); free(o->hist); free(o->hist_next); free(o);
 }
@@ -566,8 +594,8 @@ static void one_step(orc *o) {
         jy += EY[a] * v;
       }
       o->rho[k] = r;
-      o->ux[k] = (jx + 0.5 * o->p.fx / o->p.gamma) / r;
-      o->uy[k] = (jy + 0.5 * o->p.fy / o->p.gamma) / r;
+      o->ux[k] = (jx + 0.5 * FXN(o, k) / o->p.gamma) / r;
+      o->uy[k] = (jy + 0.5 * FYN(o, k) / o->p.gamma) / r;
     }
   /* phase 3: density gradient at the same time level (reading R7) */
 #pragma omp parallel for schedule(static)
@@ -599,7 +627,10 @@ static void one_step(orc *o) {
       if (o->solid[k]) continue;
       double fb[9], fo[9], dg[8];
       for (int a = 0; a < 9; ++a) fb[a] = FQ(o, o->fb, a, i, j);
-      orc_collide(fb, o->drx[k], o->dry[k], &o->p, o->omega4, o->omega5, fo, dg);
+      orc_params pn = o->p;  /* the node's body force */
+      pn.fx = FXN(o, k);
+      pn.fy = FYN(o, k);
+      orc_collide(fb, o->drx[k], o->dry[k], &pn, o->omega4, o->omega5, fo, dg);
       guards += dg[5] != 0.0;
       for (int a = 0; a < 9; ++a) FQ(o, o->f, a, i, j) = fo[a];
     }
