@@ -160,6 +160,17 @@ int lbm_load(lbm_ctx* ctx, const char* path);
  * storage_scale as in lbm_params.  Rebuilds cached graphs. */
 int lbm_set_storage(lbm_ctx* ctx, int32_t storage, double storage_scale);
 
+/* Per-node body force (Sec. 2 forcing with a spatially varying F, as the
+ * Hartmann and four-rolls mill flows of Sec. 6 need): fx, fy are host arrays
+ * of ny*nx doubles, copied (converted to the compute type: FP64 for F64
+ * storage, FP32 otherwise) and used at every node in place of the uniform
+ * lbm_params.fx, fy, including the F/(2 gamma) momentum shift of the
+ * exported fields.  Both NULL: back to the uniform force.  One NULL or a
+ * non-finite value: LBM_EINVAL.  Synchronises the stream and rebuilds cached
+ * graphs; kept across lbm_set_storage and initialisation, not written to
+ * checkpoints.  Reads 2 more compute values per node and step. */
+int lbm_set_force_field(lbm_ctx* ctx, const double* fx, const double* fy);
+
 /* Launch shape of the fused step: block of 64 x by threads, each thread
  * holding `rows` lattice rows (the autotuner's knobs).  Supported pairs are
  * listed by lbm_launch_shapes.  Rebuilds cached graphs. */

@@ -57,6 +57,8 @@ struct lbm_ctx {
   void* lat[2] = {nullptr, nullptr};
   uint8_t* d_solid = nullptr;  // nullptr when no solid node
   std::vector<uint8_t> h_solid;
+  std::vector<double> h_force;  // per-node body force [2][ny][nx]; empty: uniform
+  void* d_force = nullptr;      // the same in the compute type
 
   void* hist[2] = {nullptr, nullptr};
   void* ubuf = nullptr;
@@ -126,6 +128,8 @@ void enqueue_step(lbm_ctx* c, hipStream_t st) {
   a.hist_out = c->hist[c->cur ^ 1];
   a.ubuf = c->ubuf;
   a.partials = c->partials;
+  a.force = c->d_force ? c->d_force : c->ubuf;
+  a.has_force = c->d_force != nullptr;
   const void* src = c->lat[c->cur];
   void* dst = c->lat[c->cur ^ 1];
   switch (c->p.storage) {
@@ -194,26 +198,48 @@ int export_common(lbm_ctx* c, double* pops, float* ro, float* uxo, float* uyo, d
   switch (c->p.storage) {
     case LBM_STORE_F64:
       hipLaunchKernelGGL(export_kernel<StoreF64>, dim3(blocks), dim3(256), 0, c->stream,
-                         (const double*)src, g, c->kd, c->d_solid, pops, ro, uxo, uyo, rd, uxd,
-                         uyd);
+                         (const double*)src, g, c->kd, c->d_solid, (const double*)c->d_force, pops,
+                         ro, uxo, uyo, rd, uxd, uyd);
       break;
     case LBM_STORE_F32:
       hipLaunchKernelGGL(export_kernel<StoreF32>, dim3(blocks), dim3(256), 0, c->stream,
-                         (const float*)src, g, c->kf, c->d_solid, pops, ro, uxo, uyo, rd, uxd,
-                         uyd);
+                         (const float*)src, g, c->kf, c->d_solid, (const float*)c->d_force, pops,
+                         ro, uxo, uyo, rd, uxd, uyd);
       break;
     case LBM_STORE_BF16:
       hipLaunchKernelGGL(export_kernel<StoreBF16>, dim3(blocks), dim3(256), 0, c->stream,
-                         (const uint16_t*)src, g, c->kf, c->d_solid, pops, ro, uxo, uyo, rd, uxd,
-                         uyd);
+                         (const uint16_t*)src, g, c->kf, c->d_solid, (const float*)c->d_force,
+                         pops, ro, uxo, uyo, rd, uxd, uyd);
       break;
     default:
       hipLaunchKernelGGL(export_kernel<StoreF16>, dim3(blocks), dim3(256), 0, c->stream,
-                         (const _Float16*)src, g, c->kf, c->d_solid, pops, ro, uxo, uyo, rd,
-                         uxd, uyd);
+                         (const _Float16*)src, g, c->kf, c->d_solid, (const float*)c->d_force,
+                         pops, ro, uxo, uyo, rd, uxd, uyd);
       break;
   }
   HIPCHECK(hipGetLastError());
+  return LBM_OK;
+}
+
+// Device copy of the per-node force field in the current compute type and the
+// force flag of the constants (a field replaces the uniform force).
+int apply_force(lbm_ctx* c) {
+  if (c->d_force) HIPCHECK(hipFree(c->d_force));
+  c->d_force = nullptr;
+  const bool uniform = c->p.fx != 0.0 || c->p.fy != 0.0;
+  c->kd.force = c->kf.force = uniform ? 1 : 0;
+  if (c->h_force.empty()) return LBM_OK;
+  const size_t m = c->h_force.size();
+  std::vector<char> buf(m * c->csize);
+  if (c->csize == 8) {
+    std::memcpy(buf.data(), c->h_force.data(), m * sizeof(double));
+  } else {
+    float* f = reinterpret_cast<float*>(buf.data());
+    for (size_t i = 0; i < m; ++i) f[i] = float(c->h_force[i]);
+  }
+  HIPCHECK(hipMalloc(&c->d_force, buf.size()));
+  HIPCHECK(hipMemcpy(c->d_force, buf.data(), buf.size(), hipMemcpyHostToDevice));
+  c->kd.force = c->kf.force = 1;
   return LBM_OK;
 }
 
@@ -225,6 +251,7 @@ void free_ctx(lbm_ctx* c) {
     if (c->hist[i]) hipFree(c->hist[i]);
   }
   if (c->d_solid) hipFree(c->d_solid);
+  if (c->d_force) hipFree(c->d_force);
   if (c->ubuf) hipFree(c->ubuf);
   if (c->partials) hipFree(c->partials);
   if (c->result) hipFree(c->result);
@@ -658,7 +685,30 @@ int lbm_set_storage(lbm_ctx* c, int32_t storage, double storage_scale) {
       hipGraphExecDestroy(c->graph[i]);
       c->graph[i] = nullptr;
     }
-  return LBM_OK;
+  return apply_force(c);
+}
+
+int lbm_set_force_field(lbm_ctx* c, const double* fx, const double* fy) {
+  if (!c) return fail(LBM_EINVAL, "null context");
+  if ((fx == nullptr) != (fy == nullptr))
+    return fail(LBM_EINVAL, "force field: give both components or neither");
+  const size_t n = (size_t)c->grid.nx * c->grid.ny;
+  if (fx)
+    for (size_t i = 0; i < n; ++i)
+      if (!std::isfinite(fx[i]) || !std::isfinite(fy[i]))
+        return fail(LBM_EINVAL, "force field holds a non-finite value");
+  HIPCHECK(hipStreamSynchronize(c->stream));
+  c->h_force.clear();
+  if (fx) {
+    c->h_force.assign(fx, fx + n);
+    c->h_force.insert(c->h_force.end(), fy, fy + n);
+  }
+  for (int i = 0; i < 2; ++i)
+    if (c->graph[i]) {
+      hipGraphExecDestroy(c->graph[i]);
+      c->graph[i] = nullptr;
+    }
+  return apply_force(c);
 }
 
 int lbm_set_launch(lbm_ctx* c, int32_t by, int32_t rows) {

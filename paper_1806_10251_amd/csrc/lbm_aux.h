@@ -164,6 +164,7 @@ template <class S>
 __global__ __launch_bounds__(256) void export_kernel(const typename S::T* __restrict__ fa, Geom g,
                                                      Consts<typename S::C> k,
                                                      const uint8_t* __restrict__ solid,
+                                                     const typename S::C* __restrict__ force,
                                                      double* __restrict__ pops,
                                                      float* __restrict__ rho_o,
                                                      float* __restrict__ ux_o,
@@ -191,8 +192,10 @@ __global__ __launch_bounds__(256) void export_kernel(const typename S::T* __rest
   C jx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
   C jy = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
   if (k.force) {
-    jx -= C(0.5) * k.fx * k.ig;
-    jy -= C(0.5) * k.fy * k.ig;
+    // force: per-node field [2][ny][nx], or nullptr for the uniform force
+    const C fx = force ? force[i] : k.fx, fy = force ? force[np + i] : k.fy;
+    jx -= C(0.5) * fx * k.ig;
+    jy -= C(0.5) * fy * k.ig;
   }
   const C rho = k.rho0 + drho;
   const C vx = jx / rho, vy = jy / rho;

@@ -376,6 +376,8 @@ int configure(lbm_batch* b) {
       a.out_rows = ro;
       a.solid = c.solid;
       a.ubuf = c.ubuf;
+      a.force = c.ubuf;  // batch cases take the uniform force; any readable buffer
+      a.has_force = 0;
       a.partials = b->d_partials + (long long)c.tile_base * 4;
       a.hist_in = c.hist[par];
       a.hist_out = c.hist[par ^ 1];
@@ -957,12 +959,14 @@ int lbm_batch_fields(lbm_batch* b, int32_t ci, double* rho, double* ux, double* 
   const int blocks = int((np + 255) / 256);
   if (b->storage == LBM_STORE_F64)
     hipLaunchKernelGGL((export_kernel<StoreF64>), dim3(blocks), dim3(256), 0, b->stream,
-                       (const double*)c.lat[c.state_par], c.g, c.kd, c.solid, (double*)nullptr,
-                       (float*)nullptr, (float*)nullptr, (float*)nullptr, d, d + np, d + 2 * np);
+                       (const double*)c.lat[c.state_par], c.g, c.kd, c.solid,
+                       (const double*)nullptr, (double*)nullptr, (float*)nullptr, (float*)nullptr,
+                       (float*)nullptr, d, d + np, d + 2 * np);
   else
     hipLaunchKernelGGL((export_kernel<StoreF32>), dim3(blocks), dim3(256), 0, b->stream,
-                       (const float*)c.lat[c.state_par], c.g, c.kf, c.solid, (double*)nullptr,
-                       (float*)nullptr, (float*)nullptr, (float*)nullptr, d, d + np, d + 2 * np);
+                       (const float*)c.lat[c.state_par], c.g, c.kf, c.solid,
+                       (const float*)nullptr, (double*)nullptr, (float*)nullptr, (float*)nullptr,
+                       (float*)nullptr, d, d + np, d + 2 * np);
   hipError_t e = hipStreamSynchronize(b->stream);
   double* h[3] = {rho, ux, uy};
   for (int i = 0; i < 3 && e == hipSuccess; ++i)

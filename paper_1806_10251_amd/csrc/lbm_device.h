@@ -152,15 +152,16 @@ __device__ __forceinline__ void equilibrium_dev(C drho, C ux, C uy, const Consts
 }
 
 // density deviation and velocity of a post-stream node (forcing shifts the
-// momentum by F/(2 gamma))
+// momentum by F/(2 gamma)); fx, fy: the body force at this node
 template <class C>
-__device__ __forceinline__ void macro(const C d[9], const Consts<C>& k, C& drho, C& ux, C& uy) {
+__device__ __forceinline__ void macro(const C d[9], const Consts<C>& k, C fx, C fy, C& drho,
+                                      C& ux, C& uy) {
   drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
   C jx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
   C jy = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
   if (k.force) {
-    jx += C(0.5) * k.fx * k.ig;
-    jy += C(0.5) * k.fy * k.ig;
+    jx += C(0.5) * fx * k.ig;
+    jy += C(0.5) * fy * k.ig;
   }
   const C inv = rcp(k.rho0 + drho);
   ux = jx * inv;
@@ -170,11 +171,12 @@ __device__ __forceinline__ void macro(const C d[9], const Consts<C>& k, C& drho,
 // ---------------------------------------------------------------------------
 // Collision of one node (eq. 2a with the cascaded kernel of Sec. 5, or eq. 4
 // when gi == 0).  d: post-stream deviations in, post-collision deviations out.
-// drx, dry: density gradient.  Returns whether the strain guard fired.
+// drx, dry: density gradient; fx, fy: the body force at this node (used when
+// k.force).  Returns whether the strain guard fired.
 // ---------------------------------------------------------------------------
 template <class C>
-__device__ __forceinline__ int collide(C d[9], C drx, C dry, const Consts<C>& k, C& drho_o,
-                                       C& ux_o, C& uy_o) {
+__device__ __forceinline__ int collide(C d[9], C drx, C dry, const Consts<C>& k, C fx, C fy,
+                                       C& drho_o, C& ux_o, C& uy_o) {
   const C s56 = d[5] + d[6], s78 = d[7] + d[8];
   const C drho = ((d[0] + d[1]) + (d[2] + d[3])) + (d[4] + (s56 + s78));
   C jx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
@@ -187,8 +189,8 @@ __device__ __forceinline__ int collide(C d[9], C drx, C dry, const Consts<C>& k,
   C Kxyy = (d[5] - d[6]) - (d[7] - d[8]);
   C Kxxyy = s56 + s78;
   if (k.force) {
-    jx += C(0.5) * k.fx * k.ig;
-    jy += C(0.5) * k.fy * k.ig;
+    jx += C(0.5) * fx * k.ig;
+    jy += C(0.5) * fy * k.ig;
   }
   const C rho = k.rho0 + drho;
   const C inv_rho = rcp(rho);
@@ -199,14 +201,14 @@ __device__ __forceinline__ int collide(C d[9], C drx, C dry, const Consts<C>& k,
   if (k.force) {
     const C ig2 = k.ig * k.ig;
     s[0] = C(0);
-    s[1] = k.fx * k.ig;
-    s[2] = k.fy * k.ig;
-    s[3] = C(2) * k.fx * ux * ig2;
-    s[4] = C(2) * k.fy * uy * ig2;
-    s[5] = (k.fx * uy + k.fy * ux) * ig2;
-    s[6] = k.fy * ux2 + C(2) * k.fx * uxy;
-    s[7] = k.fx * uy2 + C(2) * k.fy * uxy;
-    s[8] = C(2) * (k.fx * ux * uy2 + k.fy * uy * ux2);
+    s[1] = fx * k.ig;
+    s[2] = fy * k.ig;
+    s[3] = C(2) * fx * ux * ig2;
+    s[4] = C(2) * fy * uy * ig2;
+    s[5] = (fx * uy + fy * ux) * ig2;
+    s[6] = fy * ux2 + C(2) * fx * uxy;
+    s[7] = fx * uy2 + C(2) * fy * uxy;
+    s[8] = C(2) * (fx * ux * uy2 + fy * uy * ux2);
     Kxx += C(0.5) * s[3];
     Kyy += C(0.5) * s[4];
     Kxy += C(0.5) * s[5];
@@ -322,17 +324,25 @@ __device__ __forceinline__ unsigned outlet_mask(const Geom& g, int y) {
 // Outlet links of node (nx-1, y): non-equilibrium extrapolation from node
 // (nx-2, y) at the same time level, with the convective outlet velocity
 // u* = (u*_old + U u(nx-2)) / (1 + U) and density rho0.  Returns u*.
+// force: a readable [2][ny][nx] buffer of the compute type, always loaded
+// (a conditional load here miscompiles for gfx950 inside the halo-row
+// lambda); its values are the per-node body force when has_force, else the
+// uniform k.fx, k.fy is used.
 template <class S>
 __device__ __forceinline__ void outlet_links(const typename S::T* __restrict__ fa, const Geom& g,
-                                             const Consts<typename S::C>& k,
+                                             const Consts<typename S::C>& k, bool has_force,
+                                             const typename S::C* __restrict__ force,
                                              const typename S::C* __restrict__ hist_in, int y,
                                              typename S::C d[9], typename S::C& us,
                                              typename S::C& vs) {
   using C = typename S::C;
   C d2[9];
   pull9<S>(fa, g, k, g.nx - 2, y, d2);
+  const int fi = y * g.nx + g.nx - 2;
+  const C ffx = force[fi], ffy = force[g.nx * g.ny + fi];
+  const C fx = has_force ? ffx : k.fx, fy = has_force ? ffy : k.fy;
   C r2, u2, v2;
-  macro<C>(d2, k, r2, u2, v2);
+  macro<C>(d2, k, fx, fy, r2, u2, v2);
   const C U = k.u_in_max;
   const C invU = C(1) / (C(1) + U);
   us = (hist_in[y] + U * u2) * invU;

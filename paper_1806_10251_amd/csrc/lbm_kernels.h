@@ -52,6 +52,10 @@ struct StepArgs {
   void* hist_out;
   void* ubuf;             // [2][ny][nx] previous velocity (compute type)
   double* partials;       // [ntiles][4]
+  const void* force;      // [2][ny][nx] compute type, always readable (the outlet reads
+                          // it unconditionally): the per-node body force when
+  int has_force;          // has_force != 0, else any buffer of that size (the uniform
+                          // force of the constants applies)
 };
 
 // Blocks are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8).
@@ -146,6 +150,8 @@ __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
   const int hx = lane == 0 ? x - 1 : x + 1;
   const int hc = lane == 0 ? 0 : W - 1;
   const C* hist_in = static_cast<const C*>(args.hist_in);
+  const C* force = static_cast<const C*>(args.force);
+  const bool has_force = args.has_force != 0;
 
   // rho - rho0 of one region row (main lane and, on lanes 0/63, the halo
   // column) into LDS row lr; used for the two halo rows
@@ -162,8 +168,8 @@ __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
     }
     if (OUTL) {
       C a_, b_;
-      if (ok && gx == g.nx - 1) outlet_links<S>(fa, g, k, hist_in, gy, dm, a_, b_);
-      if (hok && hgx == g.nx - 1) outlet_links<S>(fa, g, k, hist_in, hgy, dh, a_, b_);
+      if (ok && gx == g.nx - 1) outlet_links<S>(fa, g, k, has_force, force, hist_in, gy, dm, a_, b_);
+      if (hok && hgx == g.nx - 1) outlet_links<S>(fa, g, k, has_force, force, hist_in, hgy, dh, a_, b_);
     }
     s_rho[lr][lane + 1] = ok ? sum9<C>(dm) : SENT;
     if (halo_lane) s_rho[lr][hc] = hok ? sum9<C>(dh) : SENT;
@@ -193,10 +199,10 @@ __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
   if (OUTL) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      if (ok[r] && gxr[r] == g.nx - 1) outlet_links<S>(fa, g, k, hist_in, gyr[r], d[r], us[r], vs[r]);
+      if (ok[r] && gxr[r] == g.nx - 1) outlet_links<S>(fa, g, k, has_force, force, hist_in, gyr[r], d[r], us[r], vs[r]);
       if (hok[r] && hgx[r] == g.nx - 1) {
         C a_, b_;
-        outlet_links<S>(fa, g, k, hist_in, hgy[r], dh[r], a_, b_);
+        outlet_links<S>(fa, g, k, has_force, force, hist_in, hgy[r], dh[r], a_, b_);
       }
     }
   }
@@ -233,8 +239,13 @@ __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
       drx = C(0.5) * (sub(nE) - sub(nW));
       dry = C(0.5) * (sub(nN) - sub(nS));
     }
+    C fx = k.fx, fy = k.fy;
+    if (has_force) {
+      fx = force[y * g.nx + x];
+      fy = force[g.nx * g.ny + y * g.nx + x];
+    }
     C drho, ux, uy;
-    const int gd = collide<C>(d[r], drx, dry, k, drho, ux, uy);
+    const int gd = collide<C>(d[r], drx, dry, k, fx, fy, drho, ux, uy);
     finish_node<S, FL>(fb, args, k, d[r], gidx(g, x, y), y * g.nx + x, drho, ux, uy,
                        gd, acc);
     // boundary links: source of link a is the neighbour at -e_a

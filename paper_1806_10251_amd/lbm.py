@@ -31,6 +31,7 @@ EXPORTS = (
     "lbm_batch_residual", "lbm_batch_fields", "lbm_batch_set_launch", "lbm_batch_destroy",
     "lbm_set_storage", "lbm_batch_set_plateau", "lbm_batch_status", "lbm_batch_set_enabled",
     "lbm_batch_set_storage", "lbm_average_last_two", "lbm_batch_average_last_two",
+    "lbm_set_force_field",
 )
 
 
@@ -103,6 +104,7 @@ def load():
         "lbm_batch_fields": [vp, i32, vp, vp, vp],
         "lbm_batch_set_launch": [vp, i32, i32],
         "lbm_set_storage": [vp, i32, dbl],
+        "lbm_set_force_field": [vp, vp, vp],
         "lbm_batch_set_plateau": [vp, i32, dbl],
         "lbm_batch_status": [vp, vp],
         "lbm_batch_set_enabled": [vp, vp],
@@ -268,6 +270,14 @@ class Lattice:
     def set_storage(self, storage, storage_scale=0.0):
         st = STORAGE_NAMES[storage] if isinstance(storage, str) else int(storage)
         _check(load().lbm_set_storage(self._h, st, float(storage_scale)))
+
+    def set_force_field(self, fx, fy):
+        """Per-node body force (host arrays [ny][nx]); None, None: uniform force."""
+        arrs = [None if a is None else
+                np.ascontiguousarray(a, dtype=np.float64).reshape(self.ny, self.nx)
+                for a in (fx, fy)]
+        ptrs = [None if a is None else a.ctypes.data_as(ctypes.c_void_p) for a in arrs]
+        _check(load().lbm_set_force_field(self._h, *ptrs))
 
     def save(self, path):
         _check(load().lbm_save(self._h, str(path).encode()))

@@ -253,3 +253,27 @@ def random_populations(rng: SplitMix64, shape, lo=0.8, hi=1.2):
     """Positive random numbers for 'arbitrary population' tests."""
     n = int(np.prod(shape))
     return rng.uniform_array(n, lo, hi).reshape(shape)
+
+
+def four_roll_mill_force(n: int, u0: float, nu: float):
+    """Body force of the four-rolls mill flow (Sec. 6) on an n x n periodic
+    lattice, node centres at (i + 1/2) 2 pi / n: F = 2 nu k^2 u0 (sin kx sin ky,
+    cos kx cos ky), k = 2 pi / n.  Returns fx, fy as [n][n] arrays."""
+    k = 2 * math.pi / n
+    x = (np.arange(n) + 0.5) * k
+    X, Y = np.meshgrid(x, x)
+    c = 2 * nu * k * k * u0
+    return c * np.sin(X) * np.sin(Y), c * np.cos(X) * np.cos(Y)
+
+
+def hartmann_force(nx: int, ny: int, f_b: float, ha: float):
+    """Effective body force of the Hartmann flow (Sec. 6): the driving force
+    F_b plus the Lorentz force B0 dB_x/dz of the induced field, which
+    simplifies to F_b Ha cosh(Ha z / L) / sinh(Ha) across a channel of half
+    width L = ny / 2 (z = y + 1/2 - L at node centres; walls half-way).
+    Returns fx, fy as [ny][nx] arrays (fy = 0)."""
+    L = ny / 2.0
+    z = np.arange(ny) + 0.5 - L
+    col = f_b * ha * np.cosh(ha * z / L) / math.sinh(ha) if ha > 0 else np.full(ny, f_b)
+    fx = np.repeat(col[:, None], nx, axis=1)
+    return fx, np.zeros_like(fx)
