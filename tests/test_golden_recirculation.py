@@ -75,3 +75,38 @@ def test_gpu_wake_length_matches_correlation(re):
     print("[gpu-case] wake length Re", re, "L_r/D", lr, "correlation", ref, flush=True)
     assert abs(lr - ref) < 0.04 * ref, (lr, ref)
     lat.close()
+
+
+@pytest.mark.gpu
+def test_gpu_wake_length_over_the_correlation_range():
+    """The correlation's range 5 < Re < 60 at D = 32 (50 D x 8 D channel):
+    within 2 % for Re >= 20; the short wakes at low Re (L_r < D/2) approach
+    the correlation under refinement (D = 16 -> 32)."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1806_10251_amd import lbm
+    g = golden()
+    U = 0.05
+
+    def run(D, re):
+        nx, ny, x0, m = channel_case(D)
+        lat = lbm.Lattice(nx, ny, channel_sides(), solid=m, storage="f64", nu=U * D / re,
+                          gamma=0.5, u_in_max=U, check_every=100)
+        while True:
+            lat.step(5000)
+            if lat.residual < 1e-9 or lat.steps >= 400000:
+                break
+        assert lat.residual < 1e-8
+        lr = wake_length(lat.fields()[1], ny, x0, D)
+        lat.close()
+        ref = g["a"] + g["b"] * re
+        print("[gpu-case] wake length D", D, "Re", re, "L_r/D", lr, "correlation", ref, flush=True)
+        return (lr - ref) / ref
+
+    for re in (20.0, 50.0, 58.0):
+        assert abs(run(32, re)) < 0.02
+    e16, e32 = run(16, 10.0), run(32, 10.0)
+    assert abs(e32) < 0.7 * abs(e16)
+    assert abs(e32) < 0.1
+
