@@ -99,6 +99,10 @@ typedef struct {
   double fx, fy;  /* uniform body force */
   int32_t gi_correct;   /* 1: Sec. 5 kernel, 0: eq. 4 kernel */
   int32_t drho_stencil; /* 0: isotropic, 1: central difference */
+  int32_t strain_fd;    /* 0: strain rates from the non-equilibrium moments
+                           (eqs. 51-55); 1: finite differences of the velocity
+                           at the same time level (the alternative named in
+                           Sec. 5), with the density-gradient stencil */
 } orc_params;
 
 typedef struct {
@@ -112,6 +116,7 @@ typedef struct {
   double *rho, *ux, *uy;    /* macroscopic fields of the last step */
   double *uxp, *uyp;        /* fields of the step before */
   double *drx, *dry;        /* density gradient */
+  double *sxx, *syy;        /* strain rates by finite differences (strain_fd) */
   double *hist;   /* outlet history: [2][ny] velocity u* of the last column */
   double *hist_next;
   double *ffx, *ffy; /* per-node body force [ny][nx] (NULL: the uniform p.fx, p.fy) */
@@ -244,8 +249,20 @@ int orc_strain(double rho, double ux, double uy, double m3, double m4, double dr
 /* fbar: post-stream populations; drx, dry: density gradient.          */
 /* diag (optional, 8 entries): rho, ux, uy, dxux, dyuy, guarded, m3, m4 */
 /* ------------------------------------------------------------------ */
+void orc_collide_ext(const double fbar[9], double drx, double dry, const double *strain,
+                     const orc_params *p, double omega4, double omega5, double fout[9],
+                     double diag[8]);
+
 void orc_collide(const double fbar[9], double drx, double dry, const orc_params *p,
                  double omega4, double omega5, double fout[9], double diag[8]) {
+  orc_collide_ext(fbar, drx, dry, NULL, p, omega4, omega5, fout, diag);
+}
+
+/* As orc_collide; strain (optional, 2 entries): d_x u_x and d_y u_y to use in
+ * the corrections instead of the estimate of eqs. 51-55. */
+void orc_collide_ext(const double fbar[9], double drx, double dry, const double *strain,
+                     const orc_params *p, double omega4, double omega5, double fout[9],
+                     double diag[8]) {
   double gamma = p->gamma;
   double mb[9];
   orc_raw_moments(fbar, mb);
@@ -277,7 +294,12 @@ void orc_collide(const double fbar[9], double drx, double dry, const orc_params 
     double B = 1.0 / (gamma * gamma) - 1.0 / gamma;
     double C = 1.0 / gamma - 1.0;
     double h3 = 1.0 / w3 - 0.5, h4 = 1.0 / w4 - 0.5, h5 = 1.0 / w5 - 0.5;
-    guarded = orc_strain(rho, ux, uy, m3, m4, drx, dry, w3, w4, gamma, &dxux, &dyuy);
+    if (strain) {
+      dxux = strain[0];
+      dyuy = strain[1];
+    } else {
+      guarded = orc_strain(rho, ux, uy, m3, m4, drx, dry, w3, w4, gamma, &dxux, &dyuy);
+    }
     /* eq. 45: theta^3, lambda^3 */
     double th3x = -h3 * rho * (A * ux2 + B * uy2);
     double th3y = -h3 * rho * (A * uy2 + B * ux2);
@@ -411,10 +433,13 @@ static void outlet_links(orc *o, int j) {
   o->hist_next[1 * ny + j] = vs;
 }
 
-static double nb_rho(const orc *o, int i, int j, int di, int dj) {
+/* Value of field q at the neighbour (i+di, j+dj) for a finite difference:
+ * periodic sides wrap; a solid neighbour or one beyond a non-periodic side
+ * takes the node's own value (reading R7). */
+static double nb_val(const orc *o, const double *q, int i, int j, int di, int dj) {
   int nx = o->nx, ny = o->ny;
   int ni = i + di, nj = j + dj;
-  double own = o->rho[IDX(o, i, j)];
+  double own = q[IDX(o, i, j)];
   if (ni < 0 || ni >= nx) {
     if (o->side[ni < 0 ? SW : SE] != ORC_PERIODIC) return own;
     ni = (ni + nx) % nx;
@@ -424,7 +449,25 @@ static double nb_rho(const orc *o, int i, int j, int di, int dj) {
     nj = (nj + ny) % ny;
   }
   if (is_solid(o, ni, nj)) return own;
-  return o->rho[IDX(o, ni, nj)];
+  return q[IDX(o, ni, nj)];
+}
+
+/* d/dx and d/dy of field q at (i, j): isotropic 3 sum_a w_a e_a q(x + e_a)
+ * or central differences (drho_stencil). */
+static void fd_grad(const orc *o, const double *q, int i, int j, double *gx, double *gy) {
+  double x = 0.0, y = 0.0;
+  if (o->p.drho_stencil == 0) {
+    for (int a = 1; a < 9; ++a) {
+      double v = nb_val(o, q, i, j, EX[a], EY[a]);
+      x += 3.0 * WT[a] * EX[a] * v;
+      y += 3.0 * WT[a] * EY[a] * v;
+    }
+  } else {
+    x = 0.5 * (nb_val(o, q, i, j, 1, 0) - nb_val(o, q, i, j, -1, 0));
+    y = 0.5 * (nb_val(o, q, i, j, 0, 1) - nb_val(o, q, i, j, 0, -1));
+  }
+  *gx = x;
+  *gy = y;
 }
 
 static int valid_sides(const int side[4]) {
@@ -438,6 +481,13 @@ static int valid_sides(const int side[4]) {
 }
 
 double orc_omega_from_nu(double nu, double gamma) { return 1.0 / (3.0 * nu / gamma + 0.5); }
+
+static void free_orc(orc *o) {
+  free(o->ffx); free(o->ffy);
+  free(o->solid); free(o->f); free(o->fb); free(o->rho); free(o->ux); free(o->uy);
+  free(o->uxp); free(o->uyp); free(o->drx); free(o->dry); free(o->sxx); free(o->syy);
+  free(o->hist); free(o->hist_next); free(o);
+}
 
 orc *orc_create(int nx, int ny, const int32_t side[4], const uint8_t *solid,
                 const orc_params *p) {
@@ -465,12 +515,13 @@ orc *orc_create(int nx, int ny, const int32_t side[4], const uint8_t *solid,
   o->uyp = (double *)calloc(n, sizeof(double));
   o->drx = (double *)calloc(n, sizeof(double));
   o->dry = (double *)calloc(n, sizeof(double));
+  o->sxx = (double *)calloc(n, sizeof(double));
+  o->syy = (double *)calloc(n, sizeof(double));
   o->hist = (double *)calloc(2 * (size_t)ny, sizeof(double));
   o->hist_next = (double *)calloc(2 * (size_t)ny, sizeof(double));
   if (!o->solid || !o->f || !o->fb || !o->rho || !o->ux || !o->uy || !o->uxp ||
-      !o->uyp || !o->drx || !o->dry || !o->hist || !o->hist_next) {
-    free(o->solid); free(o->f); free(o->fb); free(o->rho); free(o->ux); free(o->uy);
-    free(o->uxp); free(o->uyp); free(o->drx); free(o->dry); free(o->hist); free(o->hist_next); free(o);
+      !o->uyp || !o->drx || !o->dry || !o->sxx || !o->syy || !o->hist || !o->hist_next) {
+    free_orc(o);
     return NULL;
   }
   if (solid) memcpy(o->solid, solid, n);
@@ -488,8 +539,7 @@ orc *orc_create(int nx, int ny, const int32_t side[4], const uint8_t *solid,
   }
   {
     if (o->p.gamma == 0) {
-      free(o->solid); free(o->f); free(o->fb); free(o->rho); free(o->ux); free(o->uy);
-      free(o->uxp); free(o->uyp); free(o->drx); free(o->dry); free(o->hist); free(o->hist_next); free(o);
+      free_orc(o);
       return NULL;
     }
   }
@@ -521,10 +571,7 @@ int orc_set_force_field(orc *o, const double *fx, const double *fy) {
 }
 
 void orc_destroy(orc *o) {
-  if (!o) return;
-  free(o->ffx); free(o->ffy);
-  free(o->solid); free(o->f); free(o->fb); free(o->rho); free(o->ux); free(o->uy);
-  free(o->uxp); free(o->uyp); free(o->drx); free(o->dry); free(o->hist); free(o->hist_next); free(o);
+  if (o) free_orc(o);
 }
 
 /* Initial state: equilibrium at the given fields (NULL -> rho0, zero velocity).
@@ -603,20 +650,12 @@ static void one_step(orc *o) {
     for (int i = 0; i < nx; ++i) {
       size_t k = IDX(o, i, j);
       if (o->solid[k]) continue;
-      double gx = 0.0, gy = 0.0;
-      if (o->p.drho_stencil == 0) {
-        /* isotropic: d rho = 3 sum_a w_a e_a rho(x + e_a) */
-        for (int a = 1; a < 9; ++a) {
-          double r = nb_rho(o, i, j, EX[a], EY[a]);
-          gx += 3.0 * WT[a] * EX[a] * r;
-          gy += 3.0 * WT[a] * EY[a] * r;
-        }
-      } else {
-        gx = 0.5 * (nb_rho(o, i, j, 1, 0) - nb_rho(o, i, j, -1, 0));
-        gy = 0.5 * (nb_rho(o, i, j, 0, 1) - nb_rho(o, i, j, 0, -1));
+      fd_grad(o, o->rho, i, j, &o->drx[k], &o->dry[k]);
+      if (o->p.strain_fd) {
+        double t;
+        fd_grad(o, o->ux, i, j, &o->sxx[k], &t);
+        fd_grad(o, o->uy, i, j, &t, &o->syy[k]);
       }
-      o->drx[k] = gx;
-      o->dry[k] = gy;
     }
   /* phase 4: collision (eq. 2a) */
   int64_t guards = 0;
@@ -630,7 +669,9 @@ static void one_step(orc *o) {
       orc_params pn = o->p;  /* the node's body force */
       pn.fx = FXN(o, k);
       pn.fy = FYN(o, k);
-      orc_collide(fb, o->drx[k], o->dry[k], &pn, o->omega4, o->omega5, fo, dg);
+      double st[2] = {o->sxx[k], o->syy[k]};
+      orc_collide_ext(fb, o->drx[k], o->dry[k], o->p.strain_fd ? st : NULL, &pn, o->omega4,
+                      o->omega5, fo, dg);
       guards += dg[5] != 0.0;
       for (int a = 0; a < 9; ++a) FQ(o, o->f, a, i, j) = fo[a];
     }

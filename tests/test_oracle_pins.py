@@ -303,10 +303,10 @@ def test_strain_estimator_matches_finite_differences(oracle_lib, gamma):
 # The GI property: shear-wave decay independent of the background velocity
 # ---------------------------------------------------------------------------
 
-def _diag_wave_rate(n, m, steps, gamma, ux0, gi):
+def _diag_wave_rate(n, m, steps, gamma, ux0, gi, strain_fd=0):
     nu_ratio = 0.05       # nu/gamma = (1/w - 1/2)/3
     o = oracle.Oracle(n, n, periodic_sides(), nu=nu_ratio * gamma, gamma=gamma,
-                      gi_correct=gi)
+                      gi_correct=gi, strain_fd=strain_fd)
     o.init_fields(*diagonal_shear_wave(n, 1e-3, m, ux0))
     k = 2 * math.pi * m / n
     x = np.arange(n) + 0.5
@@ -342,6 +342,21 @@ def test_shear_wave_decay_is_galilean_invariant(oracle_lib, gamma):
     assert spread_c < 2e-3
     assert spread_u > 10 * spread_c
     assert spread_u > (0.02 if gamma == 1.0 else 0.05)
+
+
+def test_shear_wave_decay_is_galilean_invariant_with_fd_strain(oracle_lib):
+    """The same GI property with the strain rates of the corrections taken
+    from finite differences of the velocity (the alternative of Sec. 5)."""
+    n, m, steps, gamma = 64, 1, 2000, 0.5
+    rc = [_diag_wave_rate(n, m, steps, gamma, u, 1, strain_fd=1) for u in (0.0, 0.05, 0.1)]
+    ru = [_diag_wave_rate(n, m, steps, gamma, u, 0) for u in (0.0, 0.1)]
+    exact = rc[0][1]
+    corr = [r for r, _ in rc]
+    spread_c = (max(corr) - min(corr)) / exact
+    spread_u = abs(ru[1][0] - ru[0][0]) / exact
+    assert abs(corr[0] - exact) / exact < 2e-3
+    assert spread_c < 3e-3
+    assert spread_u > 10 * spread_c
 
 
 def test_axis_shear_wave_control(oracle_lib):
