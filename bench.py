@@ -52,11 +52,13 @@ def cpu_baseline(n, U, re, gamma, budget_s=12.0):
                       f"steps, FP64, {el:.1f} s"}
 
 
-# Kernel sources whose HBM byte counters the committed traffic summary holds;
-# the figure is reported only while their hash matches.
+# Kernel sources and the build script (its compile flags) for which the
+# committed traffic summary holds HBM byte counters; the figure is reported
+# only while their hash matches.
 TRAFFIC_SOURCES = ("paper_1806_10251_amd/csrc/lbm_kernels.h",
                    "paper_1806_10251_amd/csrc/lbm_device.h",
-                   "paper_1806_10251_amd/csrc/lbm_step_f32.hip")
+                   "paper_1806_10251_amd/csrc/lbm_step_f32.hip",
+                   "paper_1806_10251_amd/build.py")
 TRAFFIC_SUMMARY = "profiles/step_f32_cavity1024_hbm_traffic.md"
 
 
@@ -225,6 +227,29 @@ def time_to_steady(lbm, n_cases, side_hi, max_steps, seed=1806, tol=1e-8):
     return out
 
 
+def kernel_variants(lbm, n, U, re, gamma, storage, by, rows, step_ms, steps=5000, warmup=500):
+    """Step time of the same cavity with the uncorrected eq. 4 kernel and with
+    the strain rates of the corrections from finite differences of the
+    velocity, at the same launch shape (HIP events), and the cost of the GI
+    corrections over the uncorrected kernel."""
+    from workloads import cavity_sides
+    out = {"steps": steps}
+    for name, kw in (("uncorrected_eq4", dict(gi_correct=0)), ("fd_strain", dict(strain_fd=1))):
+        print(f"[bench] kernel variant {name}", file=sys.stderr, flush=True)
+        v = lbm.Lattice(n, n, cavity_sides(), storage=storage, nu=U * n / re, gamma=gamma,
+                        u_lid=U, check_every=100, **kw)
+        v.set_launch(by, rows)
+        v.step(warmup)
+        v.set_timing(True)
+        v.step(steps)
+        ms = v.last_step_ms
+        v.set_timing(False)
+        v.close()
+        out[name] = {"us_per_step": round(ms * 1e3, 2), "mlups": round(n * n / (ms * 1e-3) / 1e6, 1)}
+    out["gi_correction_cost"] = round(step_ms / (out["uncorrected_eq4"]["us_per_step"] * 1e-3) - 1, 4)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -239,6 +264,8 @@ def main():
     ap.add_argument("--tts-side", type=int, default=128)
     ap.add_argument("--tts-max-steps", type=int, default=200000)
     ap.add_argument("--no-tts", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip timing the uncorrected (eq. 4) and finite-difference-strain kernels")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 256 MiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -325,6 +352,9 @@ def main():
         "residual_at_end": resid,
         "mass_drift": mass - n * n,
     }
+    if not args.no_variants:
+        out["kernel_variants"] = kernel_variants(lbm, n, U, re, gamma, args.storage, by, rows,
+                                                 step_ms_dev)
     if not args.no_tts:
         out["time_to_steady"] = time_to_steady(lbm, args.tts_cases, args.tts_side,
                                                args.tts_max_steps)

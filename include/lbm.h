@@ -83,6 +83,12 @@ typedef struct {
   int32_t gi_correct;   /* 1: Sec. 5 kernel; 0: eq. 4 kernel (uncorrected) */
   int32_t drho_stencil; /* 0: isotropic FD (default); 1: central FD        */
   int32_t check_every;  /* K >= 1: residual/mass reduction cadence (steps) */
+  int32_t strain_fd;    /* 0: strain rates of the GI corrections from the
+                           non-equilibrium moments (eqs. 51-55, default);
+                           1: from finite differences of the velocity at the
+                           same time level (the alternative of Sec. 5), with
+                           the drho_stencil stencil; lattices only, a batch
+                           rejects it */
 } lbm_params;
 
 /* Create a lattice at rest (f = w*rho0) on the current HIP device.

@@ -172,11 +172,14 @@ __device__ __forceinline__ void macro(const C d[9], const Consts<C>& k, C fx, C 
 // Collision of one node (eq. 2a with the cascaded kernel of Sec. 5, or eq. 4
 // when gi == 0).  d: post-stream deviations in, post-collision deviations out.
 // drx, dry: density gradient; fx, fy: the body force at this node (used when
-// k.force).  Returns whether the strain guard fired.
+// k.force).  FDS: the strain rates of the corrections are sxx = d_x u_x and
+// syy = d_y u_y from finite differences instead of eqs. 51-55.  Returns
+// whether the strain guard fired.
 // ---------------------------------------------------------------------------
-template <class C>
+template <class C, bool FDS = false>
 __device__ __forceinline__ int collide(C d[9], C drx, C dry, const Consts<C>& k, C fx, C fy,
-                                       C& drho_o, C& ux_o, C& uy_o) {
+                                       C& drho_o, C& ux_o, C& uy_o, C sxx = C(0),
+                                       C syy = C(0)) {
   const C s56 = d[5] + d[6], s78 = d[7] + d[8];
   const C drho = ((d[0] + d[1]) + (d[2] + d[3])) + (d[4] + (s56 + s78));
   C jx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
@@ -226,25 +229,28 @@ __device__ __forceinline__ int collide(C d[9], C drx, C dry, const Consts<C>& k,
     const C Aux2 = k.A * ux2, Auy2 = k.A * uy2, Bux2 = k.B * ux2, Buy2 = k.B * uy2;
     // local strain rates from the 2x2 system of eqs. 51-53 (eq. 55, sign of
     // the c~1 term as given by Cramer's rule)
-    const C er = k.Cg * (C(1) / C(3)) * (ux * drx + uy * dry);
-    const C ert = k.Cg * (C(1) / C(3)) * (ux * drx - uy * dry);
-    C c1 = rho * (k.a3 - C(0.5) * (Aux2 + Buy2));
-    C c2 = rho * (k.a3 - C(0.5) * (Auy2 + Bux2));
-    C ct1 = rho * (k.a4 - C(0.5) * (Aux2 - Buy2));
-    C ct2 = rho * (k.a4 - C(0.5) * (Auy2 - Bux2));
-    C D = -(c1 * ct2 + ct1 * c2);
-    const C D0 = C(-2) * k.a3 * k.a4 * rho * rho;
-    if (D * D0 <= C(0) || fabs(D) < C(0.25) * fabs(D0)) {
-      // singular-system guard: the gamma-free (A = B = 0) system
-      c1 = c2 = rho * k.a3;
-      ct1 = ct2 = rho * k.a4;
-      D = D0;
-      guarded = 1;
+    C dxux = sxx, dyuy = syy;
+    if (!FDS) {
+      const C er = k.Cg * (C(1) / C(3)) * (ux * drx + uy * dry);
+      const C ert = k.Cg * (C(1) / C(3)) * (ux * drx - uy * dry);
+      C c1 = rho * (k.a3 - C(0.5) * (Aux2 + Buy2));
+      C c2 = rho * (k.a3 - C(0.5) * (Auy2 + Bux2));
+      C ct1 = rho * (k.a4 - C(0.5) * (Aux2 - Buy2));
+      C ct2 = rho * (k.a4 - C(0.5) * (Auy2 - Bux2));
+      C D = -(c1 * ct2 + ct1 * c2);
+      const C D0 = C(-2) * k.a3 * k.a4 * rho * rho;
+      if (D * D0 <= C(0) || fabs(D) < C(0.25) * fabs(D0)) {
+        // singular-system guard: the gamma-free (A = B = 0) system
+        c1 = c2 = rho * k.a3;
+        ct1 = ct2 = rho * k.a4;
+        D = D0;
+        guarded = 1;
+      }
+      const C R3 = m3 - er, R4 = m4 - ert;
+      const C invD = rcp(D);
+      dxux = (ct2 * R3 + c2 * R4) * invD;
+      dyuy = (ct1 * R3 - c1 * R4) * invD;
     }
-    const C R3 = m3 - er, R4 = m4 - ert;
-    const C invD = rcp(D);
-    const C dxux = (ct2 * R3 + c2 * R4) * invD;
-    const C dyuy = (ct1 * R3 - c1 * R4) * invD;
     // extended-equilibrium corrections, eqs. 33 with 45-47
     D3 = -k.h3 * rho * ((Aux2 + Buy2) * dxux + (Auy2 + Bux2) * dyuy) -
          C(2) / C(3) * k.h3 * k.Cg * (ux * drx + uy * dry);

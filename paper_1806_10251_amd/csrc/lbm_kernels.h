@@ -124,15 +124,35 @@ __device__ __forceinline__ void block_partials(double acc[4], double (*s_red)[4]
   }
 }
 
+// Velocity of a pulled region node (gx, gy: its clamped lattice coordinates)
+// into the LDS slots su, sv, for the finite-difference strain rates; zero
+// when the node is not fluid (on = false).  The force is read without a
+// branch (see outlet_links).
+template <class C>
+__device__ __forceinline__ void store_velocity(const C dd[9], bool on, int gx, int gy,
+                                               const Consts<C>& k, bool has_force,
+                                               const C* __restrict__ force, const Geom& g,
+                                               C& su, C& sv) {
+  const int fi = gy * g.nx + gx;
+  const C ffx = force[fi], ffy = force[g.nx * g.ny + fi];
+  C r_, u_, v_;
+  macro<C>(dd, k, has_force ? ffx : k.fx, has_force ? ffy : k.fy, r_, u_, v_);
+  su = on ? u_ : C(0);
+  sv = on ? v_ : C(0);
+}
+
 // One tile of the fused step (the body of both the single-lattice kernel and
 // the persistent batch kernel).  LDS: s_rho[(BY*R + 2) * 66] of type C,
-// s_red[BY * 4].
-template <class S, int BY, int R, int FL, bool OBST, bool OUTL>
+// s_red[BY * 4]; with FDS (strain rates of the corrections by finite
+// differences of the velocity) also s_u, s_v of the size of s_rho.
+template <class S, int BY, int R, int FL, bool OBST, bool OUTL, bool FDS = false>
 __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
                                           typename S::T* __restrict__ fb, const StepArgs& args,
                                           const Consts<typename S::C>& k, int tile,
                                           typename S::C (*s_rho)[kLanes + 2],
-                                          double (*s_red)[4]) {
+                                          double (*s_red)[4],
+                                          typename S::C (*s_u)[kLanes + 2] = nullptr,
+                                          typename S::C (*s_v)[kLanes + 2] = nullptr) {
   using C = typename S::C;
   constexpr int RO = BY * R;   // output rows of the tile
   constexpr int RR = RO + 2;   // region rows (one halo row above and below)
@@ -152,6 +172,7 @@ __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
   const C* hist_in = static_cast<const C*>(args.hist_in);
   const C* force = static_cast<const C*>(args.force);
   const bool has_force = args.has_force != 0;
+
 
   // rho - rho0 of one region row (main lane and, on lanes 0/63, the halo
   // column) into LDS row lr; used for the two halo rows
@@ -173,6 +194,12 @@ __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
     }
     s_rho[lr][lane + 1] = ok ? sum9<C>(dm) : SENT;
     if (halo_lane) s_rho[lr][hc] = hok ? sum9<C>(dh) : SENT;
+    if (FDS) {
+      store_velocity<C>(dm, ok, gx, gy, k, has_force, force, g, s_u[lr][lane + 1],
+                        s_v[lr][lane + 1]);
+      if (halo_lane)
+        store_velocity<C>(dh, hok, hgx, hgy, k, has_force, force, g, s_u[lr][hc], s_v[lr][hc]);
+    }
   };
 
   // ---- phase 1: one batch of loads per row (main node, halo column, mask),
@@ -210,6 +237,14 @@ __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
   for (int r = 0; r < R; ++r) {
     s_rho[w * R + r + 1][lane + 1] = ok[r] ? sum9<C>(d[r]) : SENT;
     if (halo_lane) s_rho[w * R + r + 1][hc] = hok[r] ? sum9<C>(dh[r]) : SENT;
+    if (FDS) {
+      const int lr = w * R + r + 1;
+      store_velocity<C>(d[r], ok[r], gxr[r], gyr[r], k, has_force, force, g, s_u[lr][lane + 1],
+                        s_v[lr][lane + 1]);
+      if (halo_lane)
+        store_velocity<C>(dh[r], hok[r], hgx[r], hgy[r], k, has_force, force, g, s_u[lr][hc],
+                          s_v[lr][hc]);
+    }
   }
   __syncthreads();
 
@@ -239,13 +274,30 @@ __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
       drx = C(0.5) * (sub(nE) - sub(nW));
       dry = C(0.5) * (sub(nN) - sub(nS));
     }
+    C sxx = C(0), syy = C(0);
+    if (FDS) {
+      // d_x u_x and d_y u_y with the density-gradient stencil and neighbour rule
+      auto su = [&](int rr, int cc) { return s_rho[rr][cc] == SENT ? s_u[ry][c] : s_u[rr][cc]; };
+      auto sv = [&](int rr, int cc) { return s_rho[rr][cc] == SENT ? s_v[ry][c] : s_v[rr][cc]; };
+      if (k.stencil == 0) {
+        sxx = (su(ry, c + 1) - su(ry, c - 1)) * (C(1) / C(3)) +
+              ((su(ry + 1, c + 1) - su(ry + 1, c - 1)) + (su(ry - 1, c + 1) - su(ry - 1, c - 1))) *
+                  (C(1) / C(12));
+        syy = (sv(ry + 1, c) - sv(ry - 1, c)) * (C(1) / C(3)) +
+              ((sv(ry + 1, c + 1) - sv(ry - 1, c + 1)) + (sv(ry + 1, c - 1) - sv(ry - 1, c - 1))) *
+                  (C(1) / C(12));
+      } else {
+        sxx = C(0.5) * (su(ry, c + 1) - su(ry, c - 1));
+        syy = C(0.5) * (sv(ry + 1, c) - sv(ry - 1, c));
+      }
+    }
     C fx = k.fx, fy = k.fy;
     if (has_force) {
       fx = force[y * g.nx + x];
       fy = force[g.nx * g.ny + y * g.nx + x];
     }
     C drho, ux, uy;
-    const int gd = collide<C>(d[r], drx, dry, k, fx, fy, drho, ux, uy);
+    const int gd = collide<C, FDS>(d[r], drx, dry, k, fx, fy, drho, ux, uy, sxx, syy);
     finish_node<S, FL>(fb, args, k, d[r], gidx(g, x, y), y * g.nx + x, drho, ux, uy,
                        gd, acc);
     // boundary links: source of link a is the neighbour at -e_a
@@ -271,7 +323,7 @@ __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
   if (FL == kCheck) block_partials<BY>(acc, s_red, lane, w, args.partials + (long long)tile * 4);
 }
 
-template <class S, int BY, int R, int FL, bool OBST, bool OUTL>
+template <class S, int BY, int R, int FL, bool OBST, bool OUTL, bool FDS = false>
 __global__ __launch_bounds__(kLanes* BY) void step_kernel(const typename S::T* __restrict__ fa,
                                                           typename S::T* __restrict__ fb,
                                                           const StepArgs args,
@@ -279,18 +331,23 @@ __global__ __launch_bounds__(kLanes* BY) void step_kernel(const typename S::T* _
   using C = typename S::C;
   __shared__ C s_rho[BY * R + 2][kLanes + 2];
   __shared__ double s_red[BY][4];
-  step_tile<S, BY, R, FL, OBST, OUTL>(fa, fb, args, k, xcd_tile(blockIdx.x, args.ntiles), s_rho,
-                                      s_red);
+  __shared__ C s_uv[FDS ? 2 : 1][FDS ? BY * R + 2 : 1][kLanes + 2];
+  step_tile<S, BY, R, FL, OBST, OUTL, FDS>(fa, fb, args, k, xcd_tile(blockIdx.x, args.ntiles),
+                                           s_rho, s_red, s_uv[0], s_uv[FDS ? 1 : 0]);
 }
 
-// One fused step over all tiles (one block per tile).
-void launch_step_f64(int by, int rows, int flavor, const void* src, void* dst, const StepArgs& a,
-                     const Consts<double>& k, hipStream_t st);
-void launch_step_f32(int by, int rows, int flavor, const void* src, void* dst, const StepArgs& a,
-                     const Consts<float>& k, hipStream_t st);
-void launch_step_bf16(int by, int rows, int flavor, const void* src, void* dst, const StepArgs& a,
-                      const Consts<float>& k, hipStream_t st);
-void launch_step_f16(int by, int rows, int flavor, const void* src, void* dst, const StepArgs& a,
-                     const Consts<float>& k, hipStream_t st);
+// One fused step over all tiles (one block per tile).  fds selects the
+// instantiation whose strain rates come from finite differences of the
+// velocity; it is passed here rather than in the constants because the
+// kernel-argument layout of the default step is kept as it is (one more
+// word in Consts re-packs its scalar loads and costs about 3 %).
+void launch_step_f64(int by, int rows, int flavor, bool fds, const void* src, void* dst,
+                     const StepArgs& a, const Consts<double>& k, hipStream_t st);
+void launch_step_f32(int by, int rows, int flavor, bool fds, const void* src, void* dst,
+                     const StepArgs& a, const Consts<float>& k, hipStream_t st);
+void launch_step_bf16(int by, int rows, int flavor, bool fds, const void* src, void* dst,
+                     const StepArgs& a, const Consts<float>& k, hipStream_t st);
+void launch_step_f16(int by, int rows, int flavor, bool fds, const void* src, void* dst,
+                     const StepArgs& a, const Consts<float>& k, hipStream_t st);
 
 }  // namespace lbmk
