@@ -47,9 +47,18 @@ def cpu_baseline(n, U, re, gamma, budget_s=12.0):
     o.step(steps)
     el = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    # the same oracle on one thread, a shorter sample
+    oracle.set_threads(1)
+    steps1 = max(2, steps // max(cores, 1))
+    t0 = time.perf_counter()
+    o.step(steps1)
+    el1 = time.perf_counter() - t0
+    oracle.set_threads(cores)
     return {"value": n * n * steps / el / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
             "sample": f"cavity {n}x{n} Re {re:g} gamma {gamma:g}, {steps} steps after 2 warm-up "
-                      f"steps, FP64, {el:.1f} s"}
+                      f"steps, FP64, {el:.1f} s",
+            "single_thread": {"value": n * n * steps1 / el1 / 1e6, "unit": "MLUPS",
+                              "sample": f"{steps1} further steps, {el1:.1f} s"}}
 
 
 # Kernel sources and the build script (its compile flags) for which the

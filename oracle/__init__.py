@@ -67,6 +67,8 @@ def lib():
         L.orc_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int32),
                                  ctypes.c_void_p, ctypes.POINTER(OracleParams)]
         L.orc_destroy.argtypes = [ctypes.c_void_p]
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_set_threads.restype = None
         L.orc_init_fields.argtypes = [ctypes.c_void_p, dp, dp, dp]
         L.orc_step.argtypes = [ctypes.c_void_p, ctypes.c_int64]
         L.orc_step.restype = ctypes.c_int
@@ -104,6 +106,11 @@ def make_params(nu, gamma, omega3=1.0, omega6=1.0, omega7=1.0, omega8=1.0, u_lid
                 strain_fd=0):
     return OracleParams(nu, omega3, omega6, omega7, omega8, gamma, u_lid, u_in_max, rho0,
                         fx, fy, gi_correct, drho_stencil, strain_fd)
+
+
+def set_threads(n):
+    """OpenMP threads of the oracle's loops in this process (timing only)."""
+    lib().orc_set_threads(int(n))
 
 
 def omega_from_nu(nu, gamma):

@@ -56,6 +56,7 @@
  *       the discrete system and steady convergence stalls.)
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -698,6 +699,10 @@ int orc_step(orc *o, int64_t n) {
   }
   return 0;
 }
+
+/* Threads of the OpenMP loops of later steps (timing only; results do not
+ * depend on it: the reductions are serial and in row order). */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 
 double orc_residual(const orc *o) { return o->resid; }
 double orc_mass(const orc *o) { return o->mass; }
