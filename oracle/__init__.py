@@ -39,6 +39,7 @@ class OracleParams(ctypes.Structure):
         ("gi_correct", ctypes.c_int32),
         ("drho_stencil", ctypes.c_int32),
         ("strain_fd", ctypes.c_int32),
+        ("mrt", ctypes.c_int32),
     ]
 
 
@@ -103,9 +104,9 @@ def _dp(a):
 
 def make_params(nu, gamma, omega3=1.0, omega6=1.0, omega7=1.0, omega8=1.0, u_lid=0.0,
                 u_in_max=0.0, rho0=1.0, fx=0.0, fy=0.0, gi_correct=1, drho_stencil=0,
-                strain_fd=0):
+                strain_fd=0, mrt=0):
     return OracleParams(nu, omega3, omega6, omega7, omega8, gamma, u_lid, u_in_max, rho0,
-                        fx, fy, gi_correct, drho_stencil, strain_fd)
+                        fx, fy, gi_correct, drho_stencil, strain_fd, mrt)
 
 
 def set_threads(n):

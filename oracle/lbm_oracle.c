@@ -104,6 +104,10 @@ typedef struct {
                            (eqs. 51-55); 1: finite differences of the velocity
                            at the same time level (the alternative named in
                            Sec. 5), with the density-gradient stencil */
+  int32_t mrt;          /* 0: cascaded central-moment kernel (Sec. 5 / eq. 4);
+                           1: non-orthogonal raw-moment MRT form (eq. 7 with
+                           the raw equilibria of Sec. 3 and, when gi_correct,
+                           the extended equilibria of the second-order moments) */
 } orc_params;
 
 typedef struct {
@@ -323,6 +327,33 @@ void orc_collide_ext(const double fbar[9], double drx, double dry, const double 
     third = 3.0 / gamma - 1.0 / (gamma * gamma);
   } else {
     third = 2.0;
+  }
+  if (p->mrt) {
+    /* raw-moment MRT (eq. 7): the raw moments m_b of f = fbar + S/2 in the
+     * basis of eq. 5 relax with rate w_b towards the raw equilibria of Sec. 3
+     * (second order extended by D3, D4, D5); f~ = fbar + T^-1 dm + S */
+    double e3 = 2.0 / 3.0 * rho + rho * (ux2 + uy2) / gamma + D3;
+    double e4 = rho * (ux2 - uy2) / gamma + D4;
+    double e5 = rho * ux * uy / gamma + D5;
+    double e6 = rho * uy / 3.0 + rho * ux2 * uy / (gamma * gamma);
+    double e7 = rho * ux / 3.0 + rho * ux * uy2 / (gamma * gamma);
+    double e8 = rho / 9.0 + rho * (ux2 + uy2) / 3.0 + rho * ux2 * uy2;
+    double d3 = -w3 * (Kxx + Kyy - e3);
+    double d4 = -w4 * (Kxx - Kyy - e4);
+    double d5 = -w5 * (Kxy - e5);
+    double d6 = -w6 * (Kxxy - e6);
+    double d7 = -w7 * (Kxyy - e7);
+    double d8 = -w8 * (Kxxyy - e8);
+    double dk[9] = {0.0, 0.0, 0.0, 0.5 * (d3 + d4), 0.5 * (d3 - d4), d5, d6, d7, d8};
+    double df[9], S[9];
+    orc_moments_to_pop(dk, df);
+    orc_moments_to_pop(sg, S);
+    for (int a = 0; a < 9; ++a) fout[a] = fbar[a] + df[a] + S[a];
+    if (diag) {
+      diag[0] = rho; diag[1] = ux; diag[2] = uy; diag[3] = dxux; diag[4] = dyuy;
+      diag[5] = guarded; diag[6] = m3; diag[7] = m4;
+    }
+    return;
   }
   /* cascaded kernel: Sec. 5 (gi_correct) or eq. 4 */
   double g3 = w3 / 12.0 * (-m3 + D3);

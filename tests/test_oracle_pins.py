@@ -188,6 +188,89 @@ def test_equilibrium_is_fixed_point(oracle_lib, gamma):
         assert abs(d["dxux"]) < 1e-14 and abs(d["dyuy"]) < 1e-14
 
 
+def _raw_basis():
+    """Rows of the non-orthogonal moment basis of eq. 5."""
+    return np.array([np.ones(9), EX, EY, EX ** 2 + EY ** 2, EX ** 2 - EY ** 2, EX * EY,
+                     EX ** 2 * EY, EX * EY ** 2, EX ** 2 * EY ** 2], dtype=np.float64)
+
+
+@pytest.mark.parametrize("gamma,force", [(1.0, False), (0.5, True), (0.2, False)])
+def test_mrt_form_is_raw_moment_relaxation(oracle_lib, gamma, force):
+    """Brute force for the raw-moment MRT form (eq. 7, uncorrected so that no
+    correction is retyped here): raw moments of f = fbar + S/2 in the basis
+    of eq. 5 relax towards the printed raw equilibria of Sec. 3 with the
+    rates (0, 0, 0, w3, w4, w5, w6, w7, w8); the populations follow by a
+    numerical inverse of the basis, plus the source S."""
+    T = _raw_basis()
+    Ti = np.linalg.inv(T)
+    rng = SplitMix64(21)
+    fx, fy = (2e-4, -1e-4) if force else (0.0, 0.0)
+    nu, w3, w6, w7, w8 = 0.04, 1.3, 0.9, 1.1, 1.2
+    w4 = oracle.omega_from_nu(nu, gamma)
+    for _ in range(8):
+        fb = random_state(rng)
+        fo, d = oracle.collide(fb, 0.0, 0.0, nu=nu, gamma=gamma, fx=fx, fy=fy, omega3=w3,
+                               omega6=w6, omega7=w7, omega8=w8, gi_correct=0, mrt=1)
+        rho = fb.sum()
+        ux = ((EX * fb).sum() + 0.5 * fx / gamma) / rho
+        uy = ((EY * fb).sum() + 0.5 * fy / gamma) / rho
+        # source: raw moments of S listed in Sec. 3, mapped by the numerical inverse
+        sk = np.array([0.0, fx / gamma, fy / gamma,
+                       (2 * fx * ux + 2 * fy * uy) / gamma ** 2,
+                       (2 * fx * ux - 2 * fy * uy) / gamma ** 2, (fx * uy + fy * ux) / gamma ** 2,
+                       fy * ux * ux + 2 * fx * ux * uy, fx * uy * uy + 2 * fy * uy * ux,
+                       2 * (fx * ux * uy * uy + fy * uy * ux * ux)])
+        S = Ti @ sk
+        m = T @ (fb + 0.5 * S)
+        eq = np.array([rho, rho * ux, rho * uy,
+                       2 * rho / 3 + rho * (ux * ux + uy * uy) / gamma,
+                       rho * (ux * ux - uy * uy) / gamma, rho * ux * uy / gamma,
+                       rho * uy / 3 + rho * ux * ux * uy / gamma ** 2,
+                       rho * ux / 3 + rho * ux * uy * uy / gamma ** 2,
+                       rho / 9 + rho * (ux * ux + uy * uy) / 3 + rho * ux * ux * uy * uy])
+        lam = np.array([0, 0, 0, w3, w4, w4, w6, w7, w8])
+        ref = fb + Ti @ (-lam * (m - eq)) + S
+        np.testing.assert_allclose(fo, ref, rtol=0, atol=2e-15)
+
+
+@pytest.mark.parametrize("gamma", [1.0, 0.4])
+def test_mrt_form_conserves_and_keeps_printed_equilibrium(oracle_lib, gamma):
+    T = _raw_basis()
+    rng = SplitMix64(8)
+    for _ in range(6):
+        fb = random_state(rng)
+        fo, _ = oracle.collide(fb, 0.002, -0.001, nu=0.05, gamma=gamma, fx=1e-4, fy=2e-4,
+                               mrt=1)
+        assert abs(fo.sum() - fb.sum()) < 1e-15
+        assert abs((EX * fo).sum() - (EX * fb).sum() - 1e-4 / gamma) < 1e-15
+        assert abs((EY * fo).sum() - (EY * fb).sum() - 2e-4 / gamma) < 1e-15
+    for (rho, ux, uy) in [(1.0, 0.0, 0.0), (1.03, 0.04, -0.02)]:
+        eq = np.array([rho, rho * ux, rho * uy,
+                       2 * rho / 3 + rho * (ux * ux + uy * uy) / gamma,
+                       rho * (ux * ux - uy * uy) / gamma, rho * ux * uy / gamma,
+                       rho * uy / 3 + rho * ux * ux * uy / gamma ** 2,
+                       rho * ux / 3 + rho * ux * uy * uy / gamma ** 2,
+                       rho / 9 + rho * (ux * ux + uy * uy) / 3 + rho * ux * ux * uy * uy])
+        feq = np.linalg.solve(T, eq)
+        fo, d = oracle.collide(feq, 0.0, 0.0, nu=0.03, gamma=gamma, omega3=1.4, mrt=1)
+        np.testing.assert_allclose(fo, feq, atol=3e-16)
+
+
+def test_shear_wave_decay_is_galilean_invariant_mrt(oracle_lib):
+    """The GI property for the raw-moment MRT form with the same extended
+    equilibria (Sec. 5 notes that such a scheme follows from the analysis)."""
+    n, m, steps, gamma = 64, 1, 2000, 0.5
+    rc = [_diag_wave_rate(n, m, steps, gamma, u, 1, mrt=1) for u in (0.0, 0.05, 0.1)]
+    ru = [_diag_wave_rate(n, m, steps, gamma, u, 0, mrt=1) for u in (0.0, 0.1)]
+    exact = rc[0][1]
+    corr = [r for r, _ in rc]
+    spread_c = (max(corr) - min(corr)) / exact
+    spread_u = abs(ru[1][0] - ru[0][0]) / exact
+    assert abs(corr[0] - exact) / exact < 2e-3
+    assert spread_c < 1e-3
+    assert spread_u > 0.05
+
+
 @pytest.mark.parametrize("gamma", [1.0, 0.3])
 def test_uniform_flow_stays_uniform(oracle_lib, gamma):
     o = oracle.Oracle(12, 10, periodic_sides(), nu=0.05, gamma=gamma)
@@ -303,10 +386,10 @@ def test_strain_estimator_matches_finite_differences(oracle_lib, gamma):
 # The GI property: shear-wave decay independent of the background velocity
 # ---------------------------------------------------------------------------
 
-def _diag_wave_rate(n, m, steps, gamma, ux0, gi, strain_fd=0):
+def _diag_wave_rate(n, m, steps, gamma, ux0, gi, strain_fd=0, mrt=0):
     nu_ratio = 0.05       # nu/gamma = (1/w - 1/2)/3
     o = oracle.Oracle(n, n, periodic_sides(), nu=nu_ratio * gamma, gamma=gamma,
-                      gi_correct=gi, strain_fd=strain_fd)
+                      gi_correct=gi, strain_fd=strain_fd, mrt=mrt)
     o.init_fields(*diagonal_shear_wave(n, 1e-3, m, ux0))
     k = 2 * math.pi * m / n
     x = np.arange(n) + 0.5
