@@ -285,13 +285,15 @@ def batch_throughput(lbm, n_cases=256, steps=1000, seed=1806):
 
 
 def kernel_variants(lbm, n, U, re, gamma, storage, by, rows, step_ms, steps=5000, warmup=500):
-    """Step time of the same cavity with the uncorrected eq. 4 kernel and with
+    """Step time of the same cavity with the uncorrected eq. 4 kernel, with
     the strain rates of the corrections from finite differences of the
-    velocity, at the same launch shape (HIP events), and the cost of the GI
-    corrections over the uncorrected kernel."""
+    velocity and with the raw-moment MRT form of the collision, at the same
+    launch shape (HIP events), and the cost of the GI corrections over the
+    uncorrected kernel."""
     from workloads import cavity_sides
     out = {"steps": steps}
-    for name, kw in (("uncorrected_eq4", dict(gi_correct=0)), ("fd_strain", dict(strain_fd=1))):
+    for name, kw in (("uncorrected_eq4", dict(gi_correct=0)), ("fd_strain", dict(strain_fd=1)),
+                     ("mrt", dict(mrt=1))):
         print(f"[bench] kernel variant {name}", file=sys.stderr, flush=True)
         v = lbm.Lattice(n, n, cavity_sides(), storage=storage, nu=U * n / re, gamma=gamma,
                         u_lid=U, check_every=100, **kw)

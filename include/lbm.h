@@ -89,6 +89,12 @@ typedef struct {
                            same time level (the alternative of Sec. 5), with
                            the drho_stencil stencil; lattices only, a batch
                            rejects it */
+  int32_t mrt;          /* 0: cascaded central-moment collision (default);
+                           1: non-orthogonal raw-moment MRT form (eq. 7 with
+                           the raw equilibria of Sec. 3 and, with gi_correct,
+                           the same extended second-order equilibria); rates
+                           (w3, w4, w5, w6, w7, w8) as for the cascaded kernel;
+                           lattices only, a batch rejects it */
 } lbm_params;
 
 /* Create a lattice at rest (f = w*rho0) on the current HIP device.

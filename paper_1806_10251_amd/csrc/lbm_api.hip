@@ -132,12 +132,12 @@ void enqueue_step(lbm_ctx* c, hipStream_t st) {
   a.has_force = c->d_force != nullptr;
   const void* src = c->lat[c->cur];
   void* dst = c->lat[c->cur ^ 1];
-  const bool fds = c->p.strain_fd != 0;
+  const int var = (c->p.strain_fd ? kVarFds : 0) | (c->p.mrt ? kVarMrt : 0);
   switch (c->p.storage) {
-    case LBM_STORE_F64: launch_step_f64(c->by, c->rows, flavor, fds, src, dst, a, c->kd, st); break;
-    case LBM_STORE_F32: launch_step_f32(c->by, c->rows, flavor, fds, src, dst, a, c->kf, st); break;
-    case LBM_STORE_BF16: launch_step_bf16(c->by, c->rows, flavor, fds, src, dst, a, c->kf, st); break;
-    default: launch_step_f16(c->by, c->rows, flavor, fds, src, dst, a, c->kf, st); break;
+    case LBM_STORE_F64: launch_step_f64(c->by, c->rows, flavor, var, src, dst, a, c->kd, st); break;
+    case LBM_STORE_F32: launch_step_f32(c->by, c->rows, flavor, var, src, dst, a, c->kf, st); break;
+    case LBM_STORE_BF16: launch_step_bf16(c->by, c->rows, flavor, var, src, dst, a, c->kf, st); break;
+    default: launch_step_f16(c->by, c->rows, flavor, var, src, dst, a, c->kf, st); break;
   }
   if (flavor == kCheck) {
     hipLaunchKernelGGL(finalize_kernel<256>, dim3(1), dim3(256), 0, st, c->partials, c->ntiles,

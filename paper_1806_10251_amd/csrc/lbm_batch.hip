@@ -567,8 +567,8 @@ int lbm_batch_create(int32_t n, const lbm_grid* grids, const uint8_t* const* mas
   const int K = params[0].check_every;
   for (int i = 0; i < n; ++i) {
     int rc = validate(&grids[i], masks ? masks[i] : nullptr, &params[i]);
-    if (!rc && params[i].strain_fd)
-      rc = fail(LBM_EINVAL, "batch cases take the strain rates from the moments (strain_fd 0)");
+    if (!rc && (params[i].strain_fd || params[i].mrt))
+      rc = fail(LBM_EINVAL, "batch cases use the default kernel (strain_fd 0, mrt 0)");
     if (rc) return fail(rc, "case " + std::to_string(i) + ": " + lbm_last_error());
     if (params[i].storage != params[0].storage ||
         (params[i].storage != LBM_STORE_F32 && params[i].storage != LBM_STORE_F64))

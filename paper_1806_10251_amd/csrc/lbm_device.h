@@ -172,11 +172,14 @@ __device__ __forceinline__ void macro(const C d[9], const Consts<C>& k, C fx, C 
 // Collision of one node (eq. 2a with the cascaded kernel of Sec. 5, or eq. 4
 // when gi == 0).  d: post-stream deviations in, post-collision deviations out.
 // drx, dry: density gradient; fx, fy: the body force at this node (used when
-// k.force).  FDS: the strain rates of the corrections are sxx = d_x u_x and
-// syy = d_y u_y from finite differences instead of eqs. 51-55.  Returns
-// whether the strain guard fired.
+// k.force).  VAR & kVarFds: the strain rates of the corrections are
+// sxx = d_x u_x and syy = d_y u_y from finite differences instead of eqs.
+// 51-55.  VAR & kVarMrt: the raw-moment MRT form of the collision (eq. 7)
+// instead of the cascaded kernel.  Returns whether the strain guard fired.
 // ---------------------------------------------------------------------------
-template <class C, bool FDS = false>
+constexpr int kVarFds = 1, kVarMrt = 2;
+
+template <class C, int VAR = 0>
 __device__ __forceinline__ int collide(C d[9], C drx, C dry, const Consts<C>& k, C fx, C fy,
                                        C& drho_o, C& ux_o, C& uy_o, C sxx = C(0),
                                        C syy = C(0)) {
@@ -230,7 +233,7 @@ __device__ __forceinline__ int collide(C d[9], C drx, C dry, const Consts<C>& k,
     // local strain rates from the 2x2 system of eqs. 51-53 (eq. 55, sign of
     // the c~1 term as given by Cramer's rule)
     C dxux = sxx, dyuy = syy;
-    if (!FDS) {
+    if constexpr (!(VAR & kVarFds)) {
       const C er = k.Cg * (C(1) / C(3)) * (ux * drx + uy * dry);
       const C ert = k.Cg * (C(1) / C(3)) * (ux * drx - uy * dry);
       C c1 = rho * (k.a3 - C(0.5) * (Aux2 + Buy2));
@@ -259,6 +262,31 @@ __device__ __forceinline__ int collide(C d[9], C drx, C dry, const Consts<C>& k,
     D5 = -k.h5 * rho * k.B * uxy * (dxux + dyuy) -
          C(1) / C(3) * k.h5 * k.Cg * (uy * drx + ux * dry);
   }
+  if constexpr ((VAR & kVarMrt) != 0) {
+    // raw-moment MRT (eq. 7): raw moments of f = fbar + S/2 in the basis of
+    // eq. 5 relax towards the raw equilibria of Sec. 3 (second order extended
+    // by D3, D4, D5); the rest background of the deviations cancels against
+    // that of the equilibria (2 rho0/3 in m3, rho0/9 in the fourth order)
+    const C ig2 = k.ig * k.ig;
+    const C c3 = -k.w3 * (m3 - D3);
+    const C c4 = -k.w4 * (m4 - D4);
+    const C c5 = -k.w5 * (Kxy - rho * uxy * k.ig - D5);
+    const C c6 = -k.w6 * (Kxxy - rho * uy * (C(1) / C(3)) - rho * ux2 * uy * ig2);
+    const C c7 = -k.w7 * (Kxyy - rho * ux * (C(1) / C(3)) - rho * ux * uy2 * ig2);
+    const C c8 = -k.w8 * (Kxxyy - drho * (C(1) / C(9)) - rho * (ux2 + uy2) * (C(1) / C(3)) -
+                          rho * ux2 * uy2);
+    // populations from the raw-moment changes (inverse of the basis)
+    const C kxx = C(0.5) * (c3 + c4), kyy = C(0.5) * (c3 - c4);
+    d[0] += c8 - c3;
+    d[1] += C(0.5) * (kxx - c7 - c8);
+    d[3] += C(0.5) * (kxx + c7 - c8);
+    d[2] += C(0.5) * (kyy - c6 - c8);
+    d[4] += C(0.5) * (kyy + c6 - c8);
+    d[5] += C(0.25) * (c5 + c6 + c7 + c8);
+    d[6] += C(0.25) * (-c5 + c6 - c7 + c8);
+    d[7] += C(0.25) * (c5 - c6 - c7 + c8);
+    d[8] += C(0.25) * (-c5 - c6 + c7 + c8);
+  } else {
   // cascaded moment changes (Sec. 5); K background parts written out:
   // Kxx = rho0/3 + Kxx(dev), Kyy likewise, Kxxyy = rho0/9 + Kxxyy(dev)
   const C r03 = k.rho0 * (C(1) / C(3));
@@ -286,6 +314,7 @@ __device__ __forceinline__ int collide(C d[9], C drx, C dry, const Consts<C>& k,
   d[6] += t2g3 - g5 - g6 + g7 + g8;
   d[7] += t2g3 + g5 + g6 + g7 + g8;
   d[8] += t2g3 - g5 + g6 - g7 + g8;
+  }
   if (k.force) {
     // S = inverse raw-moment map of sigma'
     d[0] += s[0] - s[3] - s[4] + s[8];

@@ -108,6 +108,7 @@ inline int validate(const lbm_grid* grid, const uint8_t* solid, const lbm_params
     return fail(LBM_EINVAL, "unknown storage");
   if (p->check_every < 1) return fail(LBM_EINVAL, "check_every must be >= 1");
   if (p->strain_fd != 0 && p->strain_fd != 1) return fail(LBM_EINVAL, "strain_fd must be 0 or 1");
+  if (p->mrt != 0 && p->mrt != 1) return fail(LBM_EINVAL, "mrt must be 0 or 1");
   if (!(p->omega3 >= 0 && p->omega3 < 2) || !(p->omega6 >= 0 && p->omega6 < 2) ||
       !(p->omega7 >= 0 && p->omega7 < 2) || !(p->omega8 >= 0 && p->omega8 < 2))
     return fail(LBM_EINVAL, "omega3/6/7/8 must be in (0, 2) (0 selects 1.0)");

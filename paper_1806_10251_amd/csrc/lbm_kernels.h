@@ -144,8 +144,9 @@ __device__ __forceinline__ void store_velocity(const C dd[9], bool on, int gx, i
 // One tile of the fused step (the body of both the single-lattice kernel and
 // the persistent batch kernel).  LDS: s_rho[(BY*R + 2) * 66] of type C,
 // s_red[BY * 4]; with FDS (strain rates of the corrections by finite
-// differences of the velocity) also s_u, s_v of the size of s_rho.
-template <class S, int BY, int R, int FL, bool OBST, bool OUTL, bool FDS = false>
+// differences of the velocity, VAR & kVarFds) also s_u, s_v of the size of
+// s_rho.  VAR & kVarMrt: the raw-moment MRT form of the collision.
+template <class S, int BY, int R, int FL, bool OBST, bool OUTL, int VAR = 0>
 __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
                                           typename S::T* __restrict__ fb, const StepArgs& args,
                                           const Consts<typename S::C>& k, int tile,
@@ -154,6 +155,7 @@ __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
                                           typename S::C (*s_u)[kLanes + 2] = nullptr,
                                           typename S::C (*s_v)[kLanes + 2] = nullptr) {
   using C = typename S::C;
+  constexpr bool FDS = (VAR & kVarFds) != 0;
   constexpr int RO = BY * R;   // output rows of the tile
   constexpr int RR = RO + 2;   // region rows (one halo row above and below)
   constexpr int W = kLanes + 2;
@@ -297,7 +299,7 @@ __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
       fy = force[g.nx * g.ny + y * g.nx + x];
     }
     C drho, ux, uy;
-    const int gd = collide<C, FDS>(d[r], drx, dry, k, fx, fy, drho, ux, uy, sxx, syy);
+    const int gd = collide<C, VAR>(d[r], drx, dry, k, fx, fy, drho, ux, uy, sxx, syy);
     finish_node<S, FL>(fb, args, k, d[r], gidx(g, x, y), y * g.nx + x, drho, ux, uy,
                        gd, acc);
     // boundary links: source of link a is the neighbour at -e_a
@@ -323,7 +325,7 @@ __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
   if (FL == kCheck) block_partials<BY>(acc, s_red, lane, w, args.partials + (long long)tile * 4);
 }
 
-template <class S, int BY, int R, int FL, bool OBST, bool OUTL, bool FDS = false>
+template <class S, int BY, int R, int FL, bool OBST, bool OUTL, int VAR = 0>
 __global__ __launch_bounds__(kLanes* BY) void step_kernel(const typename S::T* __restrict__ fa,
                                                           typename S::T* __restrict__ fb,
                                                           const StepArgs args,
@@ -331,23 +333,25 @@ __global__ __launch_bounds__(kLanes* BY) void step_kernel(const typename S::T* _
   using C = typename S::C;
   __shared__ C s_rho[BY * R + 2][kLanes + 2];
   __shared__ double s_red[BY][4];
+  constexpr bool FDS = (VAR & kVarFds) != 0;
   __shared__ C s_uv[FDS ? 2 : 1][FDS ? BY * R + 2 : 1][kLanes + 2];
-  step_tile<S, BY, R, FL, OBST, OUTL, FDS>(fa, fb, args, k, xcd_tile(blockIdx.x, args.ntiles),
+  step_tile<S, BY, R, FL, OBST, OUTL, VAR>(fa, fb, args, k, xcd_tile(blockIdx.x, args.ntiles),
                                            s_rho, s_red, s_uv[0], s_uv[FDS ? 1 : 0]);
 }
 
-// One fused step over all tiles (one block per tile).  fds selects the
-// instantiation whose strain rates come from finite differences of the
-// velocity; it is passed here rather than in the constants because the
-// kernel-argument layout of the default step is kept as it is (one more
-// word in Consts re-packs its scalar loads and costs about 3 %).
-void launch_step_f64(int by, int rows, int flavor, bool fds, const void* src, void* dst,
+// One fused step over all tiles (one block per tile).  var selects the
+// instantiation (kVarFds: strain rates from finite differences of the
+// velocity; kVarMrt: raw-moment MRT collision); it is passed here rather than
+// in the constants because the kernel-argument layout of the default step is
+// kept as it is (one more word in Consts re-packs its scalar loads and costs
+// about 3 %).
+void launch_step_f64(int by, int rows, int flavor, int var, const void* src, void* dst,
                      const StepArgs& a, const Consts<double>& k, hipStream_t st);
-void launch_step_f32(int by, int rows, int flavor, bool fds, const void* src, void* dst,
+void launch_step_f32(int by, int rows, int flavor, int var, const void* src, void* dst,
                      const StepArgs& a, const Consts<float>& k, hipStream_t st);
-void launch_step_bf16(int by, int rows, int flavor, bool fds, const void* src, void* dst,
+void launch_step_bf16(int by, int rows, int flavor, int var, const void* src, void* dst,
                      const StepArgs& a, const Consts<float>& k, hipStream_t st);
-void launch_step_f16(int by, int rows, int flavor, bool fds, const void* src, void* dst,
+void launch_step_f16(int by, int rows, int flavor, int var, const void* src, void* dst,
                      const StepArgs& a, const Consts<float>& k, hipStream_t st);
 
 }  // namespace lbmk

@@ -57,7 +57,7 @@ class Params(ctypes.Structure):
         ("fx", ctypes.c_double), ("fy", ctypes.c_double), ("storage_scale", ctypes.c_double),
         ("storage", ctypes.c_int32), ("gi_correct", ctypes.c_int32),
         ("drho_stencil", ctypes.c_int32), ("check_every", ctypes.c_int32),
-        ("strain_fd", ctypes.c_int32),
+        ("strain_fd", ctypes.c_int32), ("mrt", ctypes.c_int32),
     ]
 
 
@@ -158,10 +158,10 @@ def make_grid(nx, ny, sides):
 
 def make_params(nu, gamma, storage="f32", omega3=1.0, omega6=1.0, omega7=1.0, omega8=1.0,
                 u_lid=0.0, u_in_max=0.0, rho0=1.0, fx=0.0, fy=0.0, storage_scale=0.0,
-                gi_correct=1, drho_stencil=0, check_every=1, strain_fd=0):
+                gi_correct=1, drho_stencil=0, check_every=1, strain_fd=0, mrt=0):
     st = STORAGE_NAMES[storage] if isinstance(storage, str) else int(storage)
     return Params(nu, omega3, omega6, omega7, omega8, gamma, u_lid, u_in_max, rho0, fx, fy,
-                  storage_scale, st, gi_correct, drho_stencil, check_every, strain_fd)
+                  storage_scale, st, gi_correct, drho_stencil, check_every, strain_fd, mrt)
 
 
 def launch_shapes():
