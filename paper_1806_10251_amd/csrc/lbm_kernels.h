@@ -146,7 +146,7 @@ __device__ __forceinline__ void store_velocity(const C dd[9], bool on, int gx, i
 // s_red[BY * 4]; with FDS (strain rates of the corrections by finite
 // differences of the velocity, VAR & kVarFds) also s_u, s_v of the size of
 // s_rho.  VAR & kVarMrt: the raw-moment MRT form of the collision.
-template <class S, int BY, int R, int FL, bool OBST, bool OUTL, int VAR = 0>
+template <class S, int BY, int R, int FL, bool OBST, bool OUTL, int VAR = 0, bool INT = false>
 __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
                                           typename S::T* __restrict__ fb, const StepArgs& args,
                                           const Consts<typename S::C>& k, int tile,
@@ -180,8 +180,8 @@ __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
   // column) into LDS row lr; used for the two halo rows
   auto halo_row = [&](int y, int lr) {
     int gx, gy, hgx, hgy;
-    bool ok = region_coords(g, x, y, gx, gy);
-    bool hok = halo_lane && region_coords(g, hx, y, hgx, hgy);
+    bool ok = region_coords(g, x, y, gx, gy) || INT;
+    bool hok = halo_lane && (region_coords(g, hx, y, hgx, hgy) || INT);
     C dm[9], dh[9];
     pull9<S>(fa, g, k, gx, gy, dm);
     if (halo_lane) pull9<S>(fa, g, k, hgx, hgy, dh);
@@ -214,8 +214,8 @@ __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int y = y0 + r;
-    ok[r] = region_coords(g, x, y, gxr[r], gyr[r]);
-    hok[r] = halo_lane && region_coords(g, hx, y, hgx[r], hgy[r]);
+    ok[r] = region_coords(g, x, y, gxr[r], gyr[r]) || INT;
+    hok[r] = halo_lane && (region_coords(g, hx, y, hgx[r], hgy[r]) || INT);
     pull9<S>(fa, g, k, gxr[r], gyr[r], d[r]);
     if (halo_lane) pull9<S>(fa, g, k, hgx[r], hgy[r], dh[r]);
     if (OBST) {
@@ -259,13 +259,13 @@ __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
     if (x >= g.nx || y >= g.ny) continue;
     const int c = lane + 1;
     const C own = s_rho[ry][c];
-    if (own == SENT) continue;  // solid node
+    if (!INT && own == SENT) continue;  // solid node
     // the eight neighbours, sentinel = solid or outside a non-periodic side
     const C nE = s_rho[ry][c + 1], nW = s_rho[ry][c - 1];
     const C nN = s_rho[ry + 1][c], nS = s_rho[ry - 1][c];
     const C nNE = s_rho[ry + 1][c + 1], nNW = s_rho[ry + 1][c - 1];
     const C nSE = s_rho[ry - 1][c + 1], nSW = s_rho[ry - 1][c - 1];
-    auto sub = [&](C v) { return v == SENT ? own : v; };
+    auto sub = [&](C v) { return (!INT && v == SENT) ? own : v; };
     C drx, dry;
     if (k.stencil == 0) {
       // isotropic: d rho = 3 sum_a w_a e_a rho(x + e_a)
@@ -306,7 +306,7 @@ __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
     const bool any_nf = (nE == SENT) | (nW == SENT) | (nN == SENT) | (nS == SENT) |
                         (nNE == SENT) | (nNW == SENT) | (nSE == SENT) | (nSW == SENT);
     const bool edge = x == 0 || x == g.nx - 1 || y == 0 || y == g.ny - 1;
-    if (any_nf || edge) {
+    if (!INT && (any_nf || edge)) {
       auto nonfluid = [&](int a) {
         const int sx = -ex_of(a), sy = -ey_of(a);
         const C v = sy == 0 ? (sx > 0 ? nE : nW)
@@ -335,8 +335,22 @@ __global__ __launch_bounds__(kLanes* BY) void step_kernel(const typename S::T* _
   __shared__ double s_red[BY][4];
   constexpr bool FDS = (VAR & kVarFds) != 0;
   __shared__ C s_uv[FDS ? 2 : 1][FDS ? BY * R + 2 : 1][kLanes + 2];
-  step_tile<S, BY, R, FL, OBST, OUTL, VAR>(fa, fb, args, k, xcd_tile(blockIdx.x, args.ntiles),
-                                           s_rho, s_red, s_uv[0], s_uv[FDS ? 1 : 0]);
+  const int tile = xcd_tile(blockIdx.x, args.ntiles);
+  if constexpr (!OBST && VAR == 0) {
+    // a tile whose region (with its halo ring) keeps one node away from every
+    // side has no boundary link, no solid or outside neighbour and no outlet
+    // node: it takes the path without those checks (default kernel only;
+    // measured 1.6 % faster at 1024^2)
+    const int x0 = (tile % args.tiles_x) * kLanes, y0 = (tile / args.tiles_x) * (BY * R);
+    if (x0 >= 2 && x0 + kLanes + 1 <= args.g.nx - 2 && y0 >= 2 &&
+        y0 + BY * R + 1 <= args.g.ny - 2) {
+      step_tile<S, BY, R, FL, OBST, OUTL, VAR, true>(fa, fb, args, k, tile, s_rho, s_red,
+                                                     s_uv[0], s_uv[FDS ? 1 : 0]);
+      return;
+    }
+  }
+  step_tile<S, BY, R, FL, OBST, OUTL, VAR>(fa, fb, args, k, tile, s_rho, s_red, s_uv[0],
+                                           s_uv[FDS ? 1 : 0]);
 }
 
 // One fused step over all tiles (one block per tile).  var selects the

@@ -350,3 +350,34 @@ def test_c4_channel_storage_precision_full_size(lbm):
     _say("C4 max|du|/U vs FP64", errs)
     assert errs["f32"] < 1e-5
     assert np.isfinite(errs["bf16"]) and np.isfinite(errs["f16"])
+
+
+@pytest.mark.parametrize("sides,kw", [
+    (channel_sides(), dict(nu=0.05, gamma=0.4, u_in_max=0.05)),
+    (periodic_sides(), dict(nu=0.04, gamma=0.6)),
+], ids=["channel-outlet", "periodic"])
+def test_interior_and_boundary_tiles_every_launch_shape(lbm, sides, kw):
+    """Lattices without obstacles large enough to hold tiles away from every
+    side (the path without boundary checks) next to boundary tiles (the
+    general path): 330 x 90, every launch shape, FP64 against the oracle."""
+    nx, ny, steps = 330, 90, 120
+    init = None
+    if sides == periodic_sides():
+        rng = SplitMix64(314)
+        init = (1.0 + 0.01 * rng.uniform_array(nx * ny, -1, 1).reshape(ny, nx),
+                0.03 * rng.uniform_array(nx * ny, -1, 1).reshape(ny, nx),
+                0.03 * rng.uniform_array(nx * ny, -1, 1).reshape(ny, nx))
+    o = oracle.Oracle(nx, ny, sides, **kw)
+    if init is not None:
+        o.init_fields(*init)
+    o.step(steps)
+    fo = o.get_f()
+    for shape in lbm.launch_shapes():
+        _say("interior/boundary tiles", sides, shape)
+        g = lbm.Lattice(nx, ny, sides, storage="f64", **kw)
+        g.set_launch(*shape)
+        if init is not None:
+            g.init_fields(*init)
+        g.step(steps)
+        np.testing.assert_allclose(g.populations(), fo, rtol=0, atol=1e-13)
+        g.close()
