@@ -261,6 +261,73 @@ def _log(msg):
     print(f"[surrogate] {msg}", flush=True)
 
 
+def evaluate(net, cases, tols=(1e-8, 1e-9, 1e-10), max_steps=600000, segment=20000,
+             log=_log):
+    """Held-out evaluation of the warm start: every arm runs all cases in one
+    FP64 batch from the cold start or the prediction, with or without the
+    residual filter (WARM_FILTER), to each residual tolerance; the error of
+    an arm is max |u - u_ref| / U against a warm-start run to residual 1e-11.
+    Returns one dict per arm."""
+    import torch
+
+    def arm(name, tol, warm, filter_at):
+        n = len(cases)
+        grids = [L.make_grid(k.nx, k.ny, k.sides) for k in cases]
+        params = [L.make_params(storage="f64", check_every=100, nu=k.nu, gamma=k.gamma,
+                                u_lid=k.u_ref) for k in cases]
+        b = L.Batch(grids, [k.mask for k in cases], params)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if warm:
+            warm_init(net, cases)(0, n, b)
+        done = 0
+        for at in filter_at:
+            b.run(0.0, at - done)
+            done = at
+            b.average_last_two()
+        total = np.full(n, -1, np.int64)
+        status = np.zeros(n, np.int32)
+        active = np.ones(n, bool)
+        while done < max_steps and active.any():
+            b.set_enabled(active.astype(np.int32))
+            b.set_plateau(0, 0.9)
+            m = min(segment, max_steps - done)
+            steps = b.run(tol, m)
+            st = b.status()
+            for i in range(n):
+                if active[i] and st[i] in (1, 3):
+                    total[i] = done + abs(int(steps[i]))
+                    status[i] = st[i]
+                    active[i] = False
+            done += m
+            log(f"{name} {tol:g}: {done} steps, retired {(~active).sum()}/{n}, "
+                f"{time.perf_counter() - t0:.1f} s")
+        total[active] = done
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        fields = [b.fields(i, k.ny, k.nx)[1:] for i, k in enumerate(cases)]
+        b.close()
+        return sec, total, status, fields
+
+    _, _, st_ref, f_ref = arm("reference warm+filter", 1e-11, True, WARM_FILTER)
+    ok = [i for i in range(len(cases)) if st_ref[i] == 1]
+    plan = [("cold", tols[0], False, ())]
+    for tol in tols:
+        plan += [("cold+filter", tol, False, WARM_FILTER), ("warm+filter", tol, True, WARM_FILTER)]
+    out = []
+    for name, tol, warm, fa in plan:
+        sec, total, status, f = arm(name, tol, warm, fa)
+        err = float(max(max(np.abs(f[i][0] - f_ref[i][0]).max(),
+                            np.abs(f[i][1] - f_ref[i][1]).max()) / cases[i].u_ref
+                        for i in ok)) if ok else None
+        out.append({"arm": name, "tol": tol, "seconds": round(sec, 2),
+                    "steps_sum": int(total.sum()), "converged": int((status == 1).sum()),
+                    "cases": len(cases), "reference_converged": len(ok),
+                    "max_err_vs_ref": err})
+        log("RESULT " + str(out[-1]))
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -276,7 +343,29 @@ def main(argv=None):
     bt = sub.add_parser("bench-train")
     bt.add_argument("--steps", type=int, default=50)
     bt.add_argument("--batch", type=int, default=16)
+    ev = sub.add_parser("evaluate", help="held-out warm-start evaluation (FP64 batches)")
+    ev.add_argument("--cases", type=int, default=64)
+    ev.add_argument("--side", type=int, default=512)
+    ev.add_argument("--seed", type=int, default=5151)
+    ev.add_argument("--weights", default=os.path.join(os.path.dirname(__file__), "weights",
+                                                      "unet_cavity128.npy"))
+    ev.add_argument("--tols", default="1e-8,1e-9,1e-10")
+    ev.add_argument("--max-steps", type=int, default=600000)
     args = ap.parse_args(argv)
+    if args.cmd == "evaluate":
+        import json
+        import torch
+        if not torch.cuda.is_available():
+            sys.exit("needs a GPU")
+        L.load()
+        U.load()
+        net = U.UNet(max_batch=16, res=RES, seed=0)
+        load_into(net, args.weights)
+        rows = evaluate(net, cavity_cases(args.cases, args.seed, args.side),
+                        tols=tuple(float(t) for t in args.tols.split(",")),
+                        max_steps=args.max_steps)
+        print(json.dumps(rows), flush=True)
+        return
     if args.cmd == "bench-train":
         import torch
         if not torch.cuda.is_available():
