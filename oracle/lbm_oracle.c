@@ -24,6 +24,12 @@
  *   - viscosity / gamma map ........... eq. 49 and Sec. 2 (nu = gamma/3 (1/w - 1/2))
  *   - boundaries ...................... Sec. 6 (half-way bounce-back, moving lid,
  *                                       parabolic inlet, convective outlet)
+ *   - per-node body force ............. Sec. 6 (Hartmann, four-rolls mill)
+ *   - strain rates by finite differences, raw-moment MRT form: the two
+ *     alternatives Sec. 5 names (options strain_fd, mrt)
+ *   - steady-state residual ........... not defined in the paper (it plots
+ *     histories only): ||u^{n+1}-u^n||_2 / ||u^n||_2 over fluid nodes, a
+ *     reading pinned against a decaying shear mode, not against the paper
  *
  * Readings taken where the paper is silent or inconsistent (each one is also
  * listed in the design notes of the repository):
@@ -54,6 +60,11 @@
  *       (Applying the convective equation to the populations themselves
  *       leaves the density level free: a uniform density drift then solves
  *       the discrete system and steady convergence stalls.)
+ *   R17 finite-difference strain rates: the velocity of the post-stream
+ *       state, the density-gradient stencil and the R7 neighbour rule.
+ *   R18 raw-moment MRT: eq. 7 in the transformed variable with the printed
+ *       raw equilibria of Sec. 3 (including the printed fourth order) and,
+ *       with gi_correct, the second-order equilibria extended by D3, D4, D5.
  */
 #include <math.h>
 #include <omp.h>

@@ -442,6 +442,22 @@ def test_shear_wave_decay_is_galilean_invariant_with_fd_strain(oracle_lib):
     assert spread_u > 10 * spread_c
 
 
+def test_residual_is_the_one_step_relative_change(oracle_lib):
+    """The steady-state residual r = ||u^{n+1} - u^n|| / ||u^n|| (the paper
+    plots it without a definition): for a single decaying shear mode at rest,
+    u^n = a^n u^0 after the transient, so r = 1 - a with a the per-step decay
+    factor, measured here from the fields 200 steps apart."""
+    n, gamma = 32, 0.5
+    o = oracle.Oracle(n, n, periodic_sides(), nu=0.05 * gamma, gamma=gamma)
+    o.init_fields(*axis_shear_wave(n, 1e-3, 1, 0.0))
+    o.step(400)
+    u0 = o.fields()[2]
+    o.step(200)
+    u1 = o.fields()[2]
+    a = (math.sqrt((u1 ** 2).sum() / (u0 ** 2).sum())) ** (1.0 / 200)
+    assert abs(o.residual - (1.0 - a)) < 1e-6 * (1.0 - a)
+
+
 def test_axis_shear_wave_control(oracle_lib):
     """Axis-aligned wave (no diagonal strain): both schemes decay at
     (nu/gamma) k^2 regardless of Ux."""
