@@ -176,8 +176,10 @@ __device__ __forceinline__ void macro(const C d[9], const Consts<C>& k, C fx, C 
 // sxx = d_x u_x and syy = d_y u_y from finite differences instead of eqs.
 // 51-55.  VAR & kVarMrt: the raw-moment MRT form of the collision (eq. 7)
 // instead of the cascaded kernel.  Returns whether the strain guard fired.
+// VAR & kVarNts changes no arithmetic: the step stores the populations with
+// non-temporal stores (lattices larger than the last-level cache).
 // ---------------------------------------------------------------------------
-constexpr int kVarFds = 1, kVarMrt = 2;
+constexpr int kVarFds = 1, kVarMrt = 2, kVarNts = 4;
 
 template <class C, int VAR = 0>
 __device__ __forceinline__ int collide(C d[9], C drx, C dry, const Consts<C>& k, C fx, C fy,

@@ -81,7 +81,9 @@ __device__ __forceinline__ C sum9(const C d[9]) {
 
 // Per-node epilogue: store populations, velocity buffer and residual partials.
 // li: index in the (framed) lattice; fi: index in the nx*ny field arrays.
-template <class S, int FL>
+// NTS: non-temporal population stores (the written lattice is not read again
+// before the next step has streamed the whole lattice through the caches).
+template <class S, int FL, bool NTS = false>
 __device__ __forceinline__ void finish_node(typename S::T* __restrict__ fb, const StepArgs& args,
                                             const Consts<typename S::C>& k, const typename S::C d[9],
                                             int li, int fi, typename S::C drho,
@@ -90,7 +92,12 @@ __device__ __forceinline__ void finish_node(typename S::T* __restrict__ fb, cons
   using C = typename S::C;
   const Geom& g = args.g;
 #pragma unroll
-  for (int a = 0; a < 9; ++a) fb[a * g.plane + li] = S::enc(d[a], k.scale);
+  for (int a = 0; a < 9; ++a) {
+    if constexpr (NTS)
+      __builtin_nontemporal_store(S::enc(d[a], k.scale), &fb[a * g.plane + li]);
+    else
+      fb[a * g.plane + li] = S::enc(d[a], k.scale);
+  }
   C* ubuf = static_cast<C*>(args.ubuf);
   const int np = g.nx * g.ny;
   if (FL == kCheck) {
@@ -300,7 +307,7 @@ __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
     }
     C drho, ux, uy;
     const int gd = collide<C, VAR>(d[r], drx, dry, k, fx, fy, drho, ux, uy, sxx, syy);
-    finish_node<S, FL>(fb, args, k, d[r], gidx(g, x, y), y * g.nx + x, drho, ux, uy,
+    finish_node<S, FL, (VAR & kVarNts) != 0>(fb, args, k, d[r], gidx(g, x, y), y * g.nx + x, drho, ux, uy,
                        gd, acc);
     // boundary links: source of link a is the neighbour at -e_a
     const bool any_nf = (nE == SENT) | (nW == SENT) | (nN == SENT) | (nS == SENT) |
@@ -336,7 +343,7 @@ __global__ __launch_bounds__(kLanes* BY) void step_kernel(const typename S::T* _
   constexpr bool FDS = (VAR & kVarFds) != 0;
   __shared__ C s_uv[FDS ? 2 : 1][FDS ? BY * R + 2 : 1][kLanes + 2];
   const int tile = xcd_tile(blockIdx.x, args.ntiles);
-  if constexpr (!OBST && VAR == 0) {
+  if constexpr (!OBST && (VAR & ~kVarNts) == 0) {
     // a tile whose region (with its halo ring) keeps one node away from every
     // side has no boundary link, no solid or outside neighbour and no outlet
     // node: it takes the path without those checks (default kernel only;

@@ -31,6 +31,7 @@ void go4(bool obst, bool outl, int var, const void* src, void* dst, const StepAr
     case 0: go4f<BY, R, FL, 0>(obst, outl, src, dst, a, k, st); break;
     case kVarFds: go4f<BY, R, FL, kVarFds>(obst, outl, src, dst, a, k, st); break;
     case kVarMrt: go4f<BY, R, FL, kVarMrt>(obst, outl, src, dst, a, k, st); break;
+    case kVarNts: go4f<BY, R, FL, kVarNts>(obst, outl, src, dst, a, k, st); break;
     default: go4f<BY, R, FL, kVarFds | kVarMrt>(obst, outl, src, dst, a, k, st); break;
   }
 }

@@ -253,6 +253,35 @@ def test_full_size_cavity_1024_fp32_against_oracle(lbm, oracle_1024):
         assert err <= 1e-5, shape
 
 
+def test_lattices_beyond_the_infinity_cache_against_oracle(lbm):
+    """Lattices whose two copies exceed 256 MiB run the instantiation with
+    non-temporal population stores: a 2048^2 FP32 cavity and a 2048 x 1024
+    FP64 channel with an obstacle and an outlet, all nodes after 20 steps
+    against the oracle."""
+    n, U = 2048, 0.1
+    _say("2048^2 f32 cavity 20 steps (non-temporal stores)")
+    o, g = run_pair(lbm, n, n, cavity_sides(), 20, storage="f32", check_every=10,
+                    nu=U * n / 1000, gamma=0.5, u_lid=U)
+    _, uxo, uyo = o.fields()
+    _, uxg, uyg = g.fields()
+    g.close()
+    err = max(np.abs(uxg - uxo).max(), np.abs(uyg - uyo).max()) / U
+    _say("max|du|/U", err)
+    assert err <= 1e-5
+    nx, ny = 2048, 1024
+    m = np.zeros((ny, nx), np.uint8)
+    m[448:576, 384:512] = 1
+    _say("2048x1024 f64 channel, obstacle, outlet, 20 steps (non-temporal stores)")
+    o, g = run_pair(lbm, nx, ny, channel_sides(), 20, solid=m, check_every=10, nu=0.05,
+                    gamma=0.3, u_in_max=0.04)
+    _, uxo, uyo = o.fields()
+    _, uxg, uyg = g.fields()
+    g.close()
+    err = max(np.abs(uxg - uxo).max(), np.abs(uyg - uyo).max()) / 0.04
+    _say("max|du|/U", err)
+    assert err <= 1e-11
+
+
 @pytest.mark.parametrize("gamma", [1.0, 0.5])
 def test_gi_shear_wave_2048_full_size(lbm, gamma):
     """Full-size GI check (2048^2 periodic, a = 1e-3, m = 16): with the
