@@ -92,6 +92,8 @@ def lib():
         L.orc_collide.argtypes = [dp, ctypes.c_double, ctypes.c_double,
                                   ctypes.POINTER(OracleParams), ctypes.c_double,
                                   ctypes.c_double, dp, dp]
+        L.orc_fd_gradient.argtypes = [ctypes.c_void_p, dp, dp, dp]
+        L.orc_fd_gradient.restype = None
         L.orc_omega_from_nu.argtypes = [ctypes.c_double, ctypes.c_double]
         L.orc_omega_from_nu.restype = ctypes.c_double
         _lib = L
@@ -195,6 +197,16 @@ class Oracle:
         f = np.ascontiguousarray(f, dtype=np.float64)
         assert f.shape == (9, self.ny, self.nx)
         lib().orc_set_f(self._h, _dp(f))
+
+    def fd_gradient(self, q):
+        """Finite-difference gradient (gx, gy) of a node field q [ny][nx] with
+        this lattice's stencil, sides and solid mask (the density-gradient
+        step; solid nodes get 0)."""
+        q = np.ascontiguousarray(q, dtype=np.float64).reshape(self.ny, self.nx)
+        gx = np.zeros_like(q)
+        gy = np.zeros_like(q)
+        lib().orc_fd_gradient(self._h, _dp(q), _dp(gx), _dp(gy))
+        return gx, gy
 
     def set_force_field(self, fx, fy):
         """Per-node body force [ny][nx] (None, None: the uniform force)."""

@@ -513,6 +513,23 @@ static void fd_grad(const orc *o, const double *q, int i, int j, double *gx, dou
   *gy = y;
 }
 
+/* Finite-difference gradient of a node field q [ny][nx] at every fluid node,
+ * with the stencil of the parameters and the neighbour rule of reading R7
+ * (the density-gradient step of Sec. 5 applies it to rho); solid nodes
+ * receive 0.  Exposed so that the stencil and the neighbour rule can be
+ * checked on their own. */
+void orc_fd_gradient(const orc *o, const double *q, double *gx, double *gy) {
+  for (int j = 0; j < o->ny; ++j)
+    for (int i = 0; i < o->nx; ++i) {
+      size_t k = IDX(o, i, j);
+      if (o->solid[k]) {
+        gx[k] = gy[k] = 0.0;
+        continue;
+      }
+      fd_grad(o, q, i, j, &gx[k], &gy[k]);
+    }
+}
+
 static int valid_sides(const int side[4]) {
   for (int s = 0; s < 4; ++s)
     if (side[s] < ORC_PERIODIC || side[s] > ORC_OUTLET) return 0;

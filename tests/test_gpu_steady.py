@@ -81,19 +81,39 @@ def test_fp32_stops_at_its_floor(mods):
     assert max(np.abs(uxa - uxf).max(), np.abs(uya - uyf).max()) / U < 1e-4
 
 
+def _oracle_steps_to(n, re, u, gamma, tol, check=100, max_steps=200000):
+    """Steps until the one-step residual first falls below tol at a check
+    step (every `check` steps, from step 2 * check on), by the FP64 oracle:
+    the same stopping rule as the GPU driver."""
+    import oracle
+    o = oracle.Oracle(n, n, cavity_sides(), nu=u * n / re, gamma=gamma, u_lid=u)
+    s = 0
+    while s < max_steps:
+        o.step(check)
+        s += check
+        if s >= 2 * check and o.residual < tol:
+            return s
+    return None
+
+
 def test_preconditioning_accelerates_convergence(mods):
     """Sec. 6: steps to steady state fall with gamma (the momentum equation
     of eq. 1 runs 1/gamma times faster while its steady state is unchanged).
     64^2 cavity, Re 100, U 0.05, FP64, residual 1e-6: gamma 0.5 and 0.25
-    against gamma 1 (the oracle takes 16300 and 8600 steps for 1 and 0.5;
-    the gain flattens below 0.5 at this Mach number: 6600 steps at 0.25)."""
+    against gamma 1.  The step counts are those of the FP64 oracle run with
+    the same stopping rule (within one check interval); the gain flattens
+    below 0.5 at this Mach number."""
     L, steady = mods
     _say("gamma sweep cavity 64x64 Re 100 U 0.05 f64 gammas 1, 0.5, 0.25")
-    rows = steady.gamma_sweep("cavity", 64, 100.0, 0.05, [1.0, 0.5, 0.25], tols=(1e-6,),
+    gammas = [1.0, 0.5, 0.25]
+    rows = steady.gamma_sweep("cavity", 64, 100.0, 0.05, gammas, tols=(1e-6,),
                               max_steps=200000)
     steps = {r["gamma"]: r["steps_to"]["1e-06"] for r in rows}
     _say("steps to 1e-6:", steps)
+    ref = {g: _oracle_steps_to(64, 100.0, 0.05, g, 1e-6) for g in gammas}
+    _say("oracle steps to 1e-6:", ref)
     assert all(r["status"] == "converged" for r in rows)
-    assert 15000 <= steps[1.0] <= 17500
+    for g in gammas:
+        assert ref[g] is not None and abs(steps[g] - ref[g]) <= 100, (g, steps[g], ref[g])
     assert steps[0.5] < 0.6 * steps[1.0]
     assert steps[0.25] < min(0.45 * steps[1.0], steps[0.5])
