@@ -66,7 +66,7 @@ def cpu_baseline(n, U, re, gamma, budget_s=12.0):
 # only while their hash matches.
 TRAFFIC_SOURCES = ("paper_1806_10251_amd/csrc/lbm_kernels.h",
                    "paper_1806_10251_amd/csrc/lbm_device.h",
-                   "paper_1806_10251_amd/csrc/lbm_step_f32.hip",
+                   "paper_1806_10251_amd/csrc/lbm_step.hip",
                    "paper_1806_10251_amd/build.py")
 TRAFFIC_SUMMARY = "profiles/step_f32_cavity1024_hbm_traffic.md"
 

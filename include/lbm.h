@@ -97,11 +97,17 @@ typedef struct {
                            lattices only, a batch rejects it */
 } lbm_params;
 
-/* Create a lattice at rest (f = w*rho0) on the current HIP device.
+/* Create a lattice at rest (f = w*rho0) on the current HIP device: the
+ * problem statement of the paper's test cases (Sec. 6: geometry with solid
+ * nodes, walls, a moving lid, a parabolic inlet and a convective outlet;
+ * viscosity nu and the preconditioning parameter gamma of Sec. 2, eq. 49).
  * solid_mask: ny*nx bytes, nonzero = solid node, NULL = all fluid; copied.
  * Errors: LBM_EINVAL for sizes < 2, a periodic side facing a non-periodic
  * one, INLET off W or OUTLET off E, gamma <= 0, nu <= 0, an unknown storage,
- * check_every < 1, or solid nodes in the two columns next to an OUTLET;
+ * check_every < 1, solid nodes in the two columns next to an OUTLET, or a
+ * lattice whose nine framed population planes would reach 2^32 bytes at the
+ * chosen storage (it is addressed with 32-bit byte offsets: up to about 10800^2
+ * nodes in FP32, 7600^2 in FP64, 15300^2 in 16-bit storage);
  * LBM_ENOMEM / LBM_EDEVICE from HIP. */
 int lbm_create(const lbm_grid* grid, const uint8_t* solid_mask, const lbm_params* params,
                lbm_ctx** out);
@@ -112,19 +118,23 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid_mask, const lbm_params
 int lbm_init_fields(lbm_ctx* ctx, const double* rho, const double* ux, const double* uy);
 
 /* Same, from device arrays of ny*nx floats (e.g. a warm-start prediction
- * already on the GPU).  NULL -> rho0 / zero velocity.  Asynchronous on the
- * context's stream: the arrays must be complete with respect to that stream
- * (synchronise the stream that wrote them, or share it via
- * lbm_set_stream). */
+ * already on the GPU).  NULL -> rho0 / zero velocity.  The arrays must be
+ * complete with respect to the context's stream (synchronise the stream that
+ * wrote them, or share it via lbm_set_stream); the call synchronises the
+ * context's stream before it returns, so the caller may free them then. */
 int lbm_init_fields_device(lbm_ctx* ctx, const float* rho, const float* ux, const float* uy);
 
 /* Queue all further work on hip_stream (a hipStream_t; NULL = the context's
  * own stream).  The stream must outlive the context or a later call here. */
 int lbm_set_stream(lbm_ctx* ctx, void* hip_stream);
 
-/* Advance n >= 0 time steps (asynchronous on the stream).  Every step whose
- * 1-based index is a multiple of check_every also reduces, in FP64, the
- * steady-state residual and the mass. */
+/* Advance n >= 0 time steps (asynchronous on the stream).  One step is
+ * eq. 2a (collision with the Sec. 5 kernel: strain estimate of eqs. 51-55,
+ * corrections of eqs. 45-47; or eq. 4 when gi_correct = 0) followed by eq. 2b
+ * (streaming, with the Sec. 6 boundary links).  Every step whose 1-based
+ * index is a multiple of check_every also reduces, in FP64, the steady-state
+ * residual and the mass.  Errors: LBM_EINVAL for n < 0 or a null context;
+ * LBM_EDEVICE when a launch fails. */
 int lbm_step(lbm_ctx* ctx, int64_t n);
 
 /* Replace the current state by the mean of the two lattices: after
@@ -138,8 +148,12 @@ int lbm_step(lbm_ctx* ctx, int64_t n);
 int lbm_average_last_two(lbm_ctx* ctx);
 
 /* Residual of the last check step, sqrt(sum |u^{n+1}-u^n|^2 / sum |u^n|^2)
- * over fluid nodes.  Synchronises.  LBM_ESTATE before the first check step;
- * LBM_EUNSTABLE (and *r set) when it is not finite. */
+ * over fluid nodes, summed in FP64.  The paper shows convergence histories
+ * to steady state (Sec. 6, lid-driven cavity and square cylinder) without
+ * defining the norm; this relative one-step change is the definition the
+ * library adopts (the stopping rule of its steady drivers).  Synchronises.
+ * LBM_ESTATE before the first check step; LBM_EUNSTABLE (and *r set) when it
+ * is not finite. */
 int lbm_residual(lbm_ctx* ctx, double* r);
 
 /* FP64 sum of rho over fluid nodes at the last check step.  Synchronises. */
@@ -153,7 +167,10 @@ int lbm_guard_count(lbm_ctx* ctx, int64_t* n);
 int lbm_steps(lbm_ctx* ctx, int64_t* n);
 
 /* Macroscopic fields of the current state into caller-owned host arrays of
- * ny*nx doubles (any may be NULL).  Solid nodes report 0.  Synchronises. */
+ * ny*nx doubles (any may be NULL): rho = sum f and rho u = sum e f - F/(2
+ * gamma) of the post-collision populations (the moments of Sec. 2 with the
+ * forcing shift of Sec. 3).  Solid nodes report 0.  Synchronises.  Errors:
+ * LBM_EINVAL for a null context; LBM_EDEVICE when a HIP call fails. */
 int lbm_fields(lbm_ctx* ctx, double* rho, double* ux, double* uy);
 
 /* Same into device arrays of ny*nx floats.  Synchronises. */
@@ -218,7 +235,8 @@ int lbm_batch_create(int32_t n, const lbm_grid* grids, const uint8_t* const* mas
 /* Equilibrium initialisation of case c from host fields (NULL -> rest). */
 int lbm_batch_init_fields(lbm_batch* b, int32_t c, const double* rho, const double* ux,
                           const double* uy);
-/* Same from device float arrays. */
+/* Same from device float arrays (complete with respect to the batch's
+ * stream; synchronises that stream before it returns). */
 int lbm_batch_init_fields_device(lbm_batch* b, int32_t c, const float* rho, const float* ux,
                                  const float* uy);
 

@@ -45,8 +45,10 @@
  *   R6  equilibrium used for initial states: the kernel's central-moment
  *       targets (raw fourth order follows the kernel, not the printed raw
  *       fourth-order equilibrium).
- *   R7  density-gradient neighbours: same time level; a solid or
- *       out-of-domain neighbour contributes rho(x); periodic sides wrap.
+ *   R7  density-gradient neighbours: same time level; periodic sides wrap;
+ *       a neighbour beyond a non-periodic side contributes the density of
+ *       its mirror image across the half-way wall (the adjacent edge node:
+ *       zero normal gradient); a solid neighbour contributes rho(x).
  *   R8  lid: momentum-augmented half-way bounce-back with rho_w = rho0; a
  *       link whose source lies outside the domain on both axes (a corner)
  *       is a stationary wall.  Inlet: the same moving-wall rule with the
@@ -476,20 +478,22 @@ static void outlet_links(orc *o, int j) {
   o->hist_next[1 * ny + j] = vs;
 }
 
-/* Value of field q at the neighbour (i+di, j+dj) for a finite difference:
- * periodic sides wrap; a solid neighbour or one beyond a non-periodic side
- * takes the node's own value (reading R7). */
+/* Value of field q at the neighbour (i+di, j+dj) for a finite difference
+ * (reading R7): periodic sides wrap; a neighbour beyond a non-periodic side
+ * (whose wall lies half-way, at -1/2 or n - 1/2) takes the value of its
+ * mirror image across that wall, the node on the lattice edge (zero normal
+ * gradient at the wall); a solid neighbour takes the node's own value. */
 static double nb_val(const orc *o, const double *q, int i, int j, int di, int dj) {
   int nx = o->nx, ny = o->ny;
   int ni = i + di, nj = j + dj;
   double own = q[IDX(o, i, j)];
   if (ni < 0 || ni >= nx) {
-    if (o->side[ni < 0 ? SW : SE] != ORC_PERIODIC) return own;
-    ni = (ni + nx) % nx;
+    if (o->side[ni < 0 ? SW : SE] != ORC_PERIODIC) ni = ni < 0 ? 0 : nx - 1;
+    else ni = (ni + nx) % nx;
   }
   if (nj < 0 || nj >= ny) {
-    if (o->side[nj < 0 ? SS : SN] != ORC_PERIODIC) return own;
-    nj = (nj + ny) % ny;
+    if (o->side[nj < 0 ? SS : SN] != ORC_PERIODIC) nj = nj < 0 ? 0 : ny - 1;
+    else nj = (nj + ny) % ny;
   }
   if (is_solid(o, ni, nj)) return own;
   return q[IDX(o, ni, nj)];

@@ -32,16 +32,30 @@ HIPFLAGS = [
 # runs that differ only in their check cadence or driver stay bit-identical.
 LBM_FLAGS = ["-ffp-contract=on"]
 
+# Compiled once per storage type and flavour of the step (see its header).
+STEP_SRC = "lbm_step.hip"
+JOBS = max(1, min(16, os.cpu_count() or 1))
+
 
 def build(verbose: bool = False) -> str:
     os.makedirs(OBJDIR, exist_ok=True)
-    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
-    objs = []
+    jobs = []
+    for src in sorted(glob.glob(os.path.join(CSRC, "*.hip"))):
+        name = os.path.basename(src)
+        if name == STEP_SRC:
+            # the fused step: one object per (storage, flavour)
+            for st in range(4):
+                for fl in range(3):
+                    jobs.append((src, f"{name}.s{st}f{fl}.o",
+                                 [f"-DLBM_STEP_STORAGE={st}", f"-DLBM_STEP_FLAVOR={fl}"]))
+        else:
+            jobs.append((src, name + ".o", []))
 
-    def compile_one(src):
-        obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
+    def compile_one(job):
+        src, objname, defs = job
+        obj = os.path.join(OBJDIR, objname)
         extra = LBM_FLAGS if os.path.basename(src).startswith("lbm_") else []
-        cmd = ["hipcc", *HIPFLAGS, *extra, "-c", src, "-o", obj]
+        cmd = ["hipcc", *HIPFLAGS, *extra, *defs, "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)
@@ -51,8 +65,8 @@ def build(verbose: bool = False) -> str:
             print(r.stderr)
         return obj
 
-    with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(compile_one, srcs))
+    with ThreadPoolExecutor(max_workers=min(JOBS, len(jobs))) as ex:
+        objs = list(ex.map(compile_one, jobs))
     tmp = LIB + ".tmp"
     cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)

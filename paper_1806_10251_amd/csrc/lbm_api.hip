@@ -15,6 +15,7 @@
 
 #include "../../include/lbm.h"
 #include "lbm_aux.h"
+#include "lbm_ctx.h"
 #include "lbm_host.h"
 #include "lbm_kernels.h"
 
@@ -28,6 +29,38 @@ thread_local std::string g_err;
 int fail(int code, const std::string& msg) {
   g_err = msg;
   return code;
+}
+
+int export_range(lbm_ctx* c, long long first, long long count, double* pops, float* ro,
+                 float* uxo, float* uyo, double* rd, double* uxd, double* uyd) {
+  const Geom g = make_geom_for(c->grid.nx, c->grid.ny, c->grid.side, c->esize);
+  if (count <= 0) return LBM_OK;
+  const int blocks = int((count + 255) / 256);
+  const void* src = c->lat[c->cur];
+  switch (c->p.storage) {
+    case LBM_STORE_F64:
+      hipLaunchKernelGGL(export_kernel<StoreF64>, dim3(blocks), dim3(256), 0, c->stream,
+                         (const double*)src, g, c->kd, c->d_solid, (const double*)c->d_force,
+                         first, count, pops, ro, uxo, uyo, rd, uxd, uyd);
+      break;
+    case LBM_STORE_F32:
+      hipLaunchKernelGGL(export_kernel<StoreF32>, dim3(blocks), dim3(256), 0, c->stream,
+                         (const float*)src, g, c->kf, c->d_solid, (const float*)c->d_force,
+                         first, count, pops, ro, uxo, uyo, rd, uxd, uyd);
+      break;
+    case LBM_STORE_BF16:
+      hipLaunchKernelGGL(export_kernel<StoreBF16>, dim3(blocks), dim3(256), 0, c->stream,
+                         (const uint16_t*)src, g, c->kf, c->d_solid, (const float*)c->d_force,
+                         first, count, pops, ro, uxo, uyo, rd, uxd, uyd);
+      break;
+    default:
+      hipLaunchKernelGGL(export_kernel<StoreF16>, dim3(blocks), dim3(256), 0, c->stream,
+                         (const _Float16*)src, g, c->kf, c->d_solid, (const float*)c->d_force,
+                         first, count, pops, ro, uxo, uyo, rd, uxd, uyd);
+      break;
+  }
+  HIPCHECK(hipGetLastError());
+  return LBM_OK;
 }
 }  // namespace lbmh
 
@@ -46,37 +79,6 @@ constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
 }  // namespace
 
-struct lbm_ctx {
-  lbm_grid grid{};
-  lbm_params p{};
-  int device = 0;
-  hipStream_t own_stream = nullptr;
-  hipStream_t stream = nullptr;
-  size_t esize = 4;   // bytes per stored population
-  size_t csize = 4;   // bytes per compute value
-  void* lat[2] = {nullptr, nullptr};
-  uint8_t* d_solid = nullptr;  // nullptr when no solid node
-  std::vector<uint8_t> h_solid;
-  std::vector<double> h_force;  // per-node body force [2][ny][nx]; empty: uniform
-  void* d_force = nullptr;      // the same in the compute type
-
-  void* hist[2] = {nullptr, nullptr};
-  void* ubuf = nullptr;
-  double* partials = nullptr;
-  double* result = nullptr;
-  int cur = 0;
-  int64_t t = 0;
-  bool checked = false;
-  int by = 4, rows = 1;
-  int tiles_x = 0, tiles_y = 0, ntiles = 0, out_rows = 0;
-  size_t partial_cap = 0;
-  Consts<double> kd{};
-  Consts<float> kf{};
-  hipGraphExec_t graph[2] = {nullptr, nullptr};
-  bool timing = false;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  double last_ms = -1.0;
-};
 
 namespace {
 
@@ -141,11 +143,21 @@ void enqueue_step(lbm_ctx* c, hipStream_t st) {
   // faster.
   const size_t elem = c->p.storage == LBM_STORE_F64 ? 8 : c->p.storage == LBM_STORE_F32 ? 4 : 2;
   if (var == 0 && 2 * 9 * (size_t)a.g.plane * elem > kLastLevelCacheBytes) var = kVarNts;
-  switch (c->p.storage) {
-    case LBM_STORE_F64: launch_step_f64(c->by, c->rows, flavor, var, src, dst, a, c->kd, st); break;
-    case LBM_STORE_F32: launch_step_f32(c->by, c->rows, flavor, var, src, dst, a, c->kf, st); break;
-    case LBM_STORE_BF16: launch_step_bf16(c->by, c->rows, flavor, var, src, dst, a, c->kf, st); break;
-    default: launch_step_f16(c->by, c->rows, flavor, var, src, dst, a, c->kf, st); break;
+  const void* k = c->p.storage == LBM_STORE_F64 ? static_cast<const void*>(&c->kd)
+                                                 : static_cast<const void*>(&c->kf);
+  switch (c->p.storage * 3 + flavor) {
+    case 0: launch_step<0, kPlain>(c->by, c->rows, var, src, dst, a, k, st); break;
+    case 1: launch_step<0, kStore>(c->by, c->rows, var, src, dst, a, k, st); break;
+    case 2: launch_step<0, kCheck>(c->by, c->rows, var, src, dst, a, k, st); break;
+    case 3: launch_step<1, kPlain>(c->by, c->rows, var, src, dst, a, k, st); break;
+    case 4: launch_step<1, kStore>(c->by, c->rows, var, src, dst, a, k, st); break;
+    case 5: launch_step<1, kCheck>(c->by, c->rows, var, src, dst, a, k, st); break;
+    case 6: launch_step<2, kPlain>(c->by, c->rows, var, src, dst, a, k, st); break;
+    case 7: launch_step<2, kStore>(c->by, c->rows, var, src, dst, a, k, st); break;
+    case 8: launch_step<2, kCheck>(c->by, c->rows, var, src, dst, a, k, st); break;
+    case 9: launch_step<3, kPlain>(c->by, c->rows, var, src, dst, a, k, st); break;
+    case 10: launch_step<3, kStore>(c->by, c->rows, var, src, dst, a, k, st); break;
+    default: launch_step<3, kCheck>(c->by, c->rows, var, src, dst, a, k, st); break;
   }
   if (flavor == kCheck) {
     hipLaunchKernelGGL(finalize_kernel<256>, dim3(1), dim3(256), 0, st, c->partials, c->ntiles,
@@ -201,33 +213,8 @@ int init_common(lbm_ctx* c, const FT* rho, const FT* ux, const FT* uy) {
 
 int export_common(lbm_ctx* c, double* pops, float* ro, float* uxo, float* uyo, double* rd,
                   double* uxd, double* uyd) {
-  Geom g = make_geom(c);
-  const int blocks = int(((long long)g.nx * g.ny + 255) / 256);
-  const void* src = c->lat[c->cur];
-  switch (c->p.storage) {
-    case LBM_STORE_F64:
-      hipLaunchKernelGGL(export_kernel<StoreF64>, dim3(blocks), dim3(256), 0, c->stream,
-                         (const double*)src, g, c->kd, c->d_solid, (const double*)c->d_force, pops,
-                         ro, uxo, uyo, rd, uxd, uyd);
-      break;
-    case LBM_STORE_F32:
-      hipLaunchKernelGGL(export_kernel<StoreF32>, dim3(blocks), dim3(256), 0, c->stream,
-                         (const float*)src, g, c->kf, c->d_solid, (const float*)c->d_force, pops,
-                         ro, uxo, uyo, rd, uxd, uyd);
-      break;
-    case LBM_STORE_BF16:
-      hipLaunchKernelGGL(export_kernel<StoreBF16>, dim3(blocks), dim3(256), 0, c->stream,
-                         (const uint16_t*)src, g, c->kf, c->d_solid, (const float*)c->d_force,
-                         pops, ro, uxo, uyo, rd, uxd, uyd);
-      break;
-    default:
-      hipLaunchKernelGGL(export_kernel<StoreF16>, dim3(blocks), dim3(256), 0, c->stream,
-                         (const _Float16*)src, g, c->kf, c->d_solid, (const float*)c->d_force,
-                         pops, ro, uxo, uyo, rd, uxd, uyd);
-      break;
-  }
-  HIPCHECK(hipGetLastError());
-  return LBM_OK;
+  return lbmh::export_range(c, 0, (long long)c->grid.nx * c->grid.ny, pops, ro, uxo, uyo, rd,
+                            uxd, uyd);
 }
 
 // Device copy of the per-node force field in the current compute type and the
@@ -399,7 +386,11 @@ int lbm_init_fields(lbm_ctx* c, const double* rho, const double* ux, const doubl
 
 int lbm_init_fields_device(lbm_ctx* c, const float* rho, const float* ux, const float* uy) {
   if (!c) return fail(LBM_EINVAL, "null context");
-  return init_common<float>(c, rho, ux, uy);
+  const int rc = init_common<float>(c, rho, ux, uy);
+  if (rc) return rc;
+  // the caller may release the arrays as soon as this returns
+  HIPCHECK(hipStreamSynchronize(c->stream));
+  return LBM_OK;
 }
 
 int lbm_step(lbm_ctx* c, int64_t n) {
@@ -643,6 +634,10 @@ int lbm_set_storage(lbm_ctx* c, int32_t storage, double storage_scale) {
   const int s1 = c->p.storage;
   const double inv1 = s1 == LBM_STORE_F64 ? double(c->kd.inv_scale) : double(c->kf.inv_scale);
   const size_t esize2 = storage_bytes(storage), csize2 = storage == LBM_STORE_F64 ? 8 : 4;
+  {
+    const int rc = check_lattice_bytes(c->grid.nx, c->grid.ny, esize2);
+    if (rc) return rc;
+  }
   const Geom g2 = make_geom_for(c->grid.nx, c->grid.ny, c->grid.side, esize2);
   const size_t np = (size_t)c->grid.nx * c->grid.ny;
   void* lat2[2] = {nullptr, nullptr};

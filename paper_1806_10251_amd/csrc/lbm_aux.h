@@ -152,19 +152,26 @@ __global__ __launch_bounds__(256) void ghost_fill_kernel(typename S::T* __restri
   const long long li = gidx(g, x, y);
 #pragma unroll
   for (int a = 0; a < 9; ++a) d[a] = S::dec(fa[a * g.plane + li], k.inv_scale);
-  auto nonfluid = [&](int a) {
-    int gx, gy;
-    return !region_node(g, solid, x - ex_of(a), y - ey_of(a), gx, gy);
-  };
-  ghost_writes<S>(fa, g, k, x, y, d, nonfluid);
+  unsigned bounce = side_links(g, x, y);
+  if (solid)
+    for (int a = 1; a < 9; ++a) {
+      int gx, gy;
+      if (region_coords(g, x - ex_of(a), y - ey_of(a), gx, gy) && solid[(long long)gy * g.nx + gx])
+        bounce |= 1u << a;
+    }
+  const unsigned leave = periodic_links(g, x, y);
+  ghost_writes<S>(fa, g, k, x, y, d, bounce, leave, bounce, leave);
 }
 
-// Decode populations (full f) or macroscopic fields of the current lattice.
+// Decode populations (full f) or macroscopic fields of the current lattice,
+// for the nodes first .. first + count - 1 (row-major node index); output
+// element o of every array belongs to node first + o.
 template <class S>
 __global__ __launch_bounds__(256) void export_kernel(const typename S::T* __restrict__ fa, Geom g,
                                                      Consts<typename S::C> k,
                                                      const uint8_t* __restrict__ solid,
                                                      const typename S::C* __restrict__ force,
+                                                     long long first, long long count,
                                                      double* __restrict__ pops,
                                                      float* __restrict__ rho_o,
                                                      float* __restrict__ ux_o,
@@ -174,8 +181,9 @@ __global__ __launch_bounds__(256) void export_kernel(const typename S::T* __rest
                                                      double* __restrict__ uy_d) {
   using C = typename S::C;
   const long long np = (long long)g.nx * g.ny;
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= np) return;
+  const long long o = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long i = first + o;
+  if (o >= count || i >= np) return;
   const long long li = gidx(g, int(i % g.nx), int(i / g.nx));
   C d[9];
 #pragma unroll
@@ -183,7 +191,7 @@ __global__ __launch_bounds__(256) void export_kernel(const typename S::T* __rest
   if (pops) {
 #pragma unroll
     for (int a = 0; a < 9; ++a)
-      pops[a * np + i] = double(d[a]) + double(w_of<C>(a)) * double(k.rho0);
+      pops[a * count + o] = double(d[a]) + double(w_of<C>(a)) * double(k.rho0);
   }
   const bool sol = solid && solid[i];
   // post-collision moments: rho is unchanged by collision; the momentum has
@@ -199,12 +207,12 @@ __global__ __launch_bounds__(256) void export_kernel(const typename S::T* __rest
   }
   const C rho = k.rho0 + drho;
   const C vx = jx / rho, vy = jy / rho;
-  if (rho_o) rho_o[i] = sol ? 0.f : float(rho);
-  if (ux_o) ux_o[i] = sol ? 0.f : float(vx);
-  if (uy_o) uy_o[i] = sol ? 0.f : float(vy);
-  if (rho_d) rho_d[i] = sol ? 0.0 : double(k.rho0) + double(drho);
-  if (ux_d) ux_d[i] = sol ? 0.0 : double(vx);
-  if (uy_d) uy_d[i] = sol ? 0.0 : double(vy);
+  if (rho_o) rho_o[o] = sol ? 0.f : float(rho);
+  if (ux_o) ux_o[o] = sol ? 0.f : float(vx);
+  if (uy_o) uy_o[o] = sol ? 0.f : float(vy);
+  if (rho_d) rho_d[o] = sol ? 0.0 : double(k.rho0) + double(drho);
+  if (ux_d) ux_d[o] = sol ? 0.0 : double(vx);
+  if (uy_d) uy_d[o] = sol ? 0.0 : double(vy);
 }
 
 

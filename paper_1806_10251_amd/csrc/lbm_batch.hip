@@ -64,17 +64,30 @@ __device__ __forceinline__ int load_flag(const int* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <class S, int BY, int R, int FL>
-__device__ __forceinline__ void run_item(const CaseDev& cd, int par, int tile,
+// Work items carry the tile index and, in bit kInteriorBit, whether the
+// tile's region (the tile with its one-node ring) is all fluid and keeps away
+// from every side: such tiles take the path without boundary, mask and outlet
+// logic.
+constexpr int kInteriorBit = 30;
+constexpr int kTileMask = (1 << kInteriorBit) - 1;
+
+template <class S, int BY, int R, int FL, int VAR = 0>
+__device__ __forceinline__ void run_item(const CaseDev& cd, int par, int item_tile,
                                          typename S::C (*s_rho)[kLanes + 2], double (*s_red)[4]) {
   using T = typename S::T;
   using C = typename S::C;
   const T* fa = static_cast<const T*>(cd.lat[par]);
   T* fb = static_cast<T*>(cd.lat[par ^ 1]);
-  if (cd.outlet)
-    step_tile<S, BY, R, FL, true, true>(fa, fb, cd.a[par], case_consts<C>(cd), tile, s_rho, s_red);
+  const int tile = item_tile & kTileMask;
+  if (item_tile >> kInteriorBit)
+    step_tile<S, BY, R, FL, false, false, VAR, true>(fa, fb, cd.a[par], case_consts<C>(cd), tile,
+                                                     s_rho, s_red);
+  else if (cd.outlet)
+    step_tile<S, BY, R, FL, true, true, VAR>(fa, fb, cd.a[par], case_consts<C>(cd), tile, s_rho,
+                                             s_red);
   else
-    step_tile<S, BY, R, FL, true, false>(fa, fb, cd.a[par], case_consts<C>(cd), tile, s_rho, s_red);
+    step_tile<S, BY, R, FL, true, false, VAR>(fa, fb, cd.a[par], case_consts<C>(cd), tile, s_rho,
+                                              s_red);
 }
 
 // Retirement state shared by both batch schedules.
@@ -167,14 +180,16 @@ struct StepLaunch {
   int par;
 };
 
-template <class S, int BY, int R, int FL>
+// NTS: non-temporal population stores (the active lattices together exceed
+// the last-level cache).
+template <class S, int BY, int R, int FL, bool NTS>
 __global__ __launch_bounds__(kLanes* BY) void batch_step_kernel(StepLaunch L) {
   __shared__ typename S::C s_rho[BY * R + 2][kLanes + 2];
   __shared__ double s_red[BY][4];
   const int it = xcd_tile(blockIdx.x, L.n_items);
   const int c = L.item_case[it];
   if (!L.active[c]) return;
-  run_item<S, BY, R, FL>(L.cases[c], L.par, L.item_tile[it], s_rho, s_red);
+  run_item<S, BY, R, FL, NTS ? kVarNts : 0>(L.cases[c], L.par, L.item_tile[it], s_rho, s_red);
 }
 
 // one block per case: residual of the check step that ends the window
@@ -203,12 +218,14 @@ __global__ __launch_bounds__(kLanes* BY) void batch_kernel(BatchArgs b) {
   for (;;) {
     if (lead) s_ticket = atomicAdd(b.ticket, 1u);
     __syncthreads();
-    const unsigned tk = s_ticket;
+    // uniform across the block: scalar registers (buffer resources and
+    // offsets derived from the case must be wave-uniform)
+    const unsigned tk = __builtin_amdgcn_readfirstlane(s_ticket);
     if (tk >= total) break;
     const int s = int(tk / unsigned(b.n_items));
     const int it = int(tk % unsigned(b.n_items));
     const int c = b.item_case[it];
-    const int tile = b.item_tile[it];
+    const int tile = b.item_tile[it];   // tile index and interior bit
     const CaseDev& cd = b.cases[c];
     // wait until case c has finished step s - 1 of this window
     if (lead) {
@@ -281,6 +298,8 @@ struct HostCase {
   uint8_t* solid = nullptr;
   int tiles_x = 0, ntiles = 0, tile_base = 0;
   size_t fluid = 0;
+  std::vector<uint8_t> h_mask;      // [ny][nx], 1 = solid
+  std::vector<uint8_t> tile_int;    // per tile: region all fluid, away from the sides
   int state_par = 0;  // which lattice holds the case's current state
 };
 
@@ -360,6 +379,22 @@ int configure(lbm_batch* b) {
     c.ntiles = c.tiles_x * ((c.grid.ny + ro - 1) / ro);
     c.tile_base = total;
     total += c.ntiles;
+    // interior tiles: the same margins as the single-lattice kernel, and no
+    // solid node in the tile or its ring
+    c.tile_int.assign(c.ntiles, 0);
+    const int nx = c.grid.nx, ny = c.grid.ny;
+    for (int t = 0; t < c.ntiles; ++t) {
+      const int x0 = (t % c.tiles_x) * kLanes, y0 = (t / c.tiles_x) * ro;
+      if (!(x0 >= 2 && x0 + kLanes + 1 <= nx - 2 && y0 >= 2 && y0 + ro + 1 <= ny - 2)) continue;
+      bool fluid = true;
+      for (int y = y0 - 1; fluid && y <= y0 + ro; ++y)
+        for (int x = x0 - 1; x <= x0 + kLanes; ++x)
+          if (c.h_mask[(size_t)y * nx + x]) {
+            fluid = false;
+            break;
+          }
+      c.tile_int[t] = fluid ? 1 : 0;
+    }
   }
   hipFree(b->d_partials);
   b->d_partials = nullptr;
@@ -414,7 +449,7 @@ int rebuild_items(lbm_batch* b) {
       if (!b->h_active[i]) continue;
       for (int t = 0; t < b->cs[i].ntiles; ++t) {
         ic.push_back(i);
-        itl.push_back(t);
+        itl.push_back(t | (int(b->cs[i].tile_int[t]) << kInteriorBit));
       }
     }
   } else {
@@ -425,7 +460,7 @@ int rebuild_items(lbm_batch* b) {
       for (int i = 0; i < b->n; ++i)
         if (b->h_active[i] && t < b->cs[i].ntiles) {
           ic.push_back(i);
-          itl.push_back(t);
+          itl.push_back(t | (int(b->cs[i].tile_int[t]) << kInteriorBit));
         }
   }
   b->n_items = (int)ic.size();
@@ -493,22 +528,40 @@ int align_parity(lbm_batch* b) {
 }
 
 
-template <class S, int BY>
-void launch_step_by(int flavor, const StepLaunch& L, hipStream_t st) {
+template <class S, int BY, bool NTS>
+void launch_step_nts(int flavor, const StepLaunch& L, hipStream_t st) {
   dim3 grid(L.n_items), block(kLanes, BY);
   if (flavor == kCheck)
-    hipLaunchKernelGGL((batch_step_kernel<S, BY, 1, kCheck>), grid, block, 0, st, L);
+    hipLaunchKernelGGL((batch_step_kernel<S, BY, 1, kCheck, NTS>), grid, block, 0, st, L);
   else if (flavor == kStore)
-    hipLaunchKernelGGL((batch_step_kernel<S, BY, 1, kStore>), grid, block, 0, st, L);
+    hipLaunchKernelGGL((batch_step_kernel<S, BY, 1, kStore, NTS>), grid, block, 0, st, L);
   else
-    hipLaunchKernelGGL((batch_step_kernel<S, BY, 1, kPlain>), grid, block, 0, st, L);
+    hipLaunchKernelGGL((batch_step_kernel<S, BY, 1, kPlain, NTS>), grid, block, 0, st, L);
+}
+
+template <class S, int BY>
+void launch_step_by(int flavor, bool nts, const StepLaunch& L, hipStream_t st) {
+  if (nts) launch_step_nts<S, BY, true>(flavor, L, st);
+  else launch_step_nts<S, BY, false>(flavor, L, st);
 }
 
 template <class S>
-void launch_step_storage(int by, int flavor, const StepLaunch& L, hipStream_t st) {
-  if (by == 8) launch_step_by<S, 8>(flavor, L, st);
-  else if (by == 16) launch_step_by<S, 16>(flavor, L, st);
-  else launch_step_by<S, 4>(flavor, L, st);
+void launch_step_storage(int by, int flavor, bool nts, const StepLaunch& L, hipStream_t st) {
+  if (by == 8) launch_step_by<S, 8>(flavor, nts, L, st);
+  else if (by == 16) launch_step_by<S, 16>(flavor, nts, L, st);
+  else launch_step_by<S, 4>(flavor, nts, L, st);
+}
+
+// Bytes of the two lattices of every active case.  Beyond the 256 MiB
+// Infinity Cache a written lattice is evicted before the next step reads it,
+// so the step stores it non-temporally (as the single-lattice path does).
+constexpr size_t kLastLevelCacheBytes = size_t(256) << 20;
+size_t active_lattice_bytes(const lbm_batch* b) {
+  const size_t es = b->storage == LBM_STORE_F64 ? 8 : 4;
+  size_t bytes = 0;
+  for (int i = 0; i < b->n; ++i)
+    if (b->h_active[i]) bytes += 2 * 9 * (size_t)b->cs[i].g.plane * es;
+  return bytes;
 }
 
 RetireArgs retire_args(lbm_batch* b, double tol, long long min_steps) {
@@ -538,14 +591,15 @@ void enqueue_window(lbm_batch* b, long long t, int nsteps, const RetireArgs& r, 
   L.n_items = b->n_items;
   L.active = b->d_active;
   int last_flavor = kPlain;
+  const bool nts = active_lattice_bytes(b) > kLastLevelCacheBytes;
   for (int i = 0; i < nsteps; ++i) {
     const long long tt = t + i;
     const long long idx = (tt + 1) % b->K;
     const int flavor = idx == 0 ? kCheck : ((b->K >= 2 && idx == b->K - 1) ? kStore : kPlain);
     L.par = int(tt & 1);
     if (L.n_items > 0) {
-      if (b->storage == LBM_STORE_F64) launch_step_storage<StoreF64>(b->by, flavor, L, st);
-      else launch_step_storage<StoreF32>(b->by, flavor, L, st);
+      if (b->storage == LBM_STORE_F64) launch_step_storage<StoreF64>(b->by, flavor, nts, L, st);
+      else launch_step_storage<StoreF32>(b->by, flavor, nts, L, st);
     }
     last_flavor = flavor;
   }
@@ -623,6 +677,7 @@ int lbm_batch_create(int32_t n, const lbm_grid* grids, const uint8_t* const* mas
         solid += hm[q];
       }
     c.fluid = np - solid;
+    c.h_mask = hm;
     ok = ok && dev(hipMalloc(&c.solid, np), "hipMalloc mask") &&
          dev(hipMemcpy(c.solid, hm.data(), np, hipMemcpyHostToDevice), "copy mask");
   }
@@ -709,7 +764,11 @@ int lbm_batch_init_fields(lbm_batch* b, int32_t ci, const double* rho, const dou
 int lbm_batch_init_fields_device(lbm_batch* b, int32_t ci, const float* rho, const float* ux,
                                  const float* uy) {  // NOLINT
   if (!b || ci < 0 || ci >= b->n) return fail(LBM_EINVAL, "bad batch or case index");
-  return init_case<float>(b, ci, rho, ux, uy);
+  const int rc = init_case<float>(b, ci, rho, ux, uy);
+  if (rc) return rc;
+  // the caller may release the arrays as soon as this returns
+  HIPCHECK(hipStreamSynchronize(b->stream));
+  return LBM_OK;
 }
 
 int lbm_batch_run(lbm_batch* b, double tol, int64_t max_steps, int64_t* steps_per_case) {
@@ -876,6 +935,10 @@ int lbm_batch_set_storage(lbm_batch* b, int32_t storage) {
   HIPCHECK(hipStreamSynchronize(b->stream));
   const size_t es2 = storage == LBM_STORE_F64 ? 8 : 4, es1 = b->storage == LBM_STORE_F64 ? 8 : 4;
   for (auto& c : b->cs) {
+    const int rc = check_lattice_bytes(c.grid.nx, c.grid.ny, es2);
+    if (rc) return rc;
+  }
+  for (auto& c : b->cs) {
     const Geom g2 = make_geom_for(c.grid.nx, c.grid.ny, c.grid.side, es2);
     const size_t np = (size_t)c.grid.nx * c.grid.ny;
     void* lat2[2] = {nullptr, nullptr};
@@ -962,12 +1025,14 @@ int lbm_batch_fields(lbm_batch* b, int32_t ci, double* rho, double* ux, double* 
   if (b->storage == LBM_STORE_F64)
     hipLaunchKernelGGL((export_kernel<StoreF64>), dim3(blocks), dim3(256), 0, b->stream,
                        (const double*)c.lat[c.state_par], c.g, c.kd, c.solid,
-                       (const double*)nullptr, (double*)nullptr, (float*)nullptr, (float*)nullptr,
+                       (const double*)nullptr, 0LL, (long long)np, (double*)nullptr, (float*)nullptr,
+                       (float*)nullptr,
                        (float*)nullptr, d, d + np, d + 2 * np);
   else
     hipLaunchKernelGGL((export_kernel<StoreF32>), dim3(blocks), dim3(256), 0, b->stream,
                        (const float*)c.lat[c.state_par], c.g, c.kf, c.solid,
-                       (const float*)nullptr, (double*)nullptr, (float*)nullptr, (float*)nullptr,
+                       (const float*)nullptr, 0LL, (long long)np, (double*)nullptr, (float*)nullptr,
+                       (float*)nullptr,
                        (float*)nullptr, d, d + np, d + 2 * np);
   hipError_t e = hipStreamSynchronize(b->stream);
   double* h[3] = {rho, ux, uy};

@@ -70,6 +70,87 @@ struct StoreF16 {
 };
 
 // ---------------------------------------------------------------------------
+// Buffer-resource access to population planes.  A plane is read or written
+// through a buffer resource whose 64-bit base already carries the plane
+// offset (and, for the pull, the streaming shift of the direction), so the
+// nine loads or stores of a node share one 32-bit byte offset and cost no
+// per-population vector address arithmetic (the bases are scalar).  The
+// resource size bounds the offset by the plane size; every legal offset is
+// smaller because of the ghost frame.
+// ---------------------------------------------------------------------------
+using Rsrc = __amdgpu_buffer_rsrc_t;
+constexpr int kRsrcWord3 = 0x00020000;  // raw 32-bit data format (gfx9 family)
+
+// One resource per lattice; the plane offset rides in the scalar offset
+// operand, so every byte offset must fit in 32 bits: the library limits one
+// lattice's nine planes to fewer than 2^32 bytes.  The size field is the
+// largest value (no range clamping); every access lies inside the lattice.
+// The base is wave-uniform by construction; reading it from the first lane
+// keeps it in scalar registers where the compiler cannot prove it uniform
+// (a case descriptor read from memory inside a persistent kernel).
+template <class T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+  const uint64_t a = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(a));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(a >> 32));
+  return reinterpret_cast<T*>((uint64_t(hi) << 32) | lo);
+}
+template <class T>
+__device__ __forceinline__ Rsrc lattice_rsrc(const T* base) {
+  return __builtin_amdgcn_make_buffer_rsrc(uniform_ptr(const_cast<T*>(base)), 0,
+                                           int(0xFFFFFFFFu), kRsrcWord3);
+}
+// Scalar byte offset (plane and streaming shift): wave-uniform by construction.
+__device__ __forceinline__ int soff(uint32_t so) { return __builtin_amdgcn_readfirstlane(int(so)); }
+
+// Raw loads/stores of one stored element; AUX 2 marks a non-temporal store.
+template <class T>
+struct Buf;
+template <>
+struct Buf<float> {
+  static __device__ __forceinline__ float ld(Rsrc r, uint32_t off, uint32_t so) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, int(off), soff(so), 0));
+  }
+  template <int AUX>
+  static __device__ __forceinline__ void st(Rsrc r, uint32_t off, uint32_t so, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, int(off), soff(so), AUX);
+  }
+};
+template <>
+struct Buf<double> {
+  using V2 = __attribute__((ext_vector_type(2))) unsigned int;
+  static __device__ __forceinline__ double ld(Rsrc r, uint32_t off, uint32_t so) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, int(off), soff(so), 0));
+  }
+  template <int AUX>
+  static __device__ __forceinline__ void st(Rsrc r, uint32_t off, uint32_t so, double v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, int(off), soff(so), AUX);
+  }
+};
+template <>
+struct Buf<uint16_t> {
+  static __device__ __forceinline__ uint16_t ld(Rsrc r, uint32_t off, uint32_t so) {
+    return __builtin_amdgcn_raw_buffer_load_b16(r, int(off), soff(so), 0);
+  }
+  template <int AUX>
+  static __device__ __forceinline__ void st(Rsrc r, uint32_t off, uint32_t so, uint16_t v) {
+    __builtin_amdgcn_raw_buffer_store_b16(v, r, int(off), soff(so), AUX);
+  }
+};
+template <>
+struct Buf<_Float16> {
+  static __device__ __forceinline__ _Float16 ld(Rsrc r, uint32_t off, uint32_t so) {
+    return __builtin_bit_cast(_Float16,
+                              __builtin_amdgcn_raw_buffer_load_b16(r, int(off), soff(so), 0));
+  }
+  template <int AUX>
+  static __device__ __forceinline__ void st(Rsrc r, uint32_t off, uint32_t so, _Float16 v) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, int(off), soff(so),
+                                          AUX);
+  }
+};
+
+// ---------------------------------------------------------------------------
 // Per-lattice constants (derived once on the host from nu, gamma, omegas).
 // ---------------------------------------------------------------------------
 template <class C>
@@ -84,6 +165,13 @@ struct Consts {
   C fx, fy;              // uniform body force
   C u_lid, u_in_max;
   C scale, inv_scale;    // storage scale (1 for F32/F64)
+  // products of the above that every node needs (formed once on the host)
+  C q3, q4, q5, q6, q7, q8;  // w3/12, w4/4, w5/4, w6/4, w7/4, w8/4
+  C cg3;                     // C_gamma / 3
+  C l3, l4, l5;              // (2/3) h3 C_gamma, (2/3) h4 C_gamma, (1/3) h5 C_gamma
+  C h5B;                     // h5 B_gamma
+  C d0;                      // -2 a3 a4
+  C r03;                     // rho0 / 3
   int gi;                // 1: Sec. 5 kernel; 0: eq. 4
   int force;             // body force present
   int stencil;           // 0 isotropic, 1 central
@@ -235,15 +323,16 @@ __device__ __forceinline__ int collide(C d[9], C drx, C dry, const Consts<C>& k,
     // local strain rates from the 2x2 system of eqs. 51-53 (eq. 55, sign of
     // the c~1 term as given by Cramer's rule)
     C dxux = sxx, dyuy = syy;
+    const C pg = ux * drx + uy * dry, mg = ux * drx - uy * dry;
     if constexpr (!(VAR & kVarFds)) {
-      const C er = k.Cg * (C(1) / C(3)) * (ux * drx + uy * dry);
-      const C ert = k.Cg * (C(1) / C(3)) * (ux * drx - uy * dry);
+      const C er = k.cg3 * pg;
+      const C ert = k.cg3 * mg;
       C c1 = rho * (k.a3 - C(0.5) * (Aux2 + Buy2));
       C c2 = rho * (k.a3 - C(0.5) * (Auy2 + Bux2));
       C ct1 = rho * (k.a4 - C(0.5) * (Aux2 - Buy2));
       C ct2 = rho * (k.a4 - C(0.5) * (Auy2 - Bux2));
       C D = -(c1 * ct2 + ct1 * c2);
-      const C D0 = C(-2) * k.a3 * k.a4 * rho * rho;
+      const C D0 = k.d0 * (rho * rho);
       if (D * D0 <= C(0) || fabs(D) < C(0.25) * fabs(D0)) {
         // singular-system guard: the gamma-free (A = B = 0) system
         c1 = c2 = rho * k.a3;
@@ -257,12 +346,9 @@ __device__ __forceinline__ int collide(C d[9], C drx, C dry, const Consts<C>& k,
       dyuy = (ct1 * R3 - c1 * R4) * invD;
     }
     // extended-equilibrium corrections, eqs. 33 with 45-47
-    D3 = -k.h3 * rho * ((Aux2 + Buy2) * dxux + (Auy2 + Bux2) * dyuy) -
-         C(2) / C(3) * k.h3 * k.Cg * (ux * drx + uy * dry);
-    D4 = -k.h4 * rho * ((Aux2 - Buy2) * dxux + (Bux2 - Auy2) * dyuy) -
-         C(2) / C(3) * k.h4 * k.Cg * (ux * drx - uy * dry);
-    D5 = -k.h5 * rho * k.B * uxy * (dxux + dyuy) -
-         C(1) / C(3) * k.h5 * k.Cg * (uy * drx + ux * dry);
+    D3 = -k.h3 * rho * ((Aux2 + Buy2) * dxux + (Auy2 + Bux2) * dyuy) - k.l3 * pg;
+    D4 = -k.h4 * rho * ((Aux2 - Buy2) * dxux + (Bux2 - Auy2) * dyuy) - k.l4 * mg;
+    D5 = -k.h5B * rho * uxy * (dxux + dyuy) - k.l5 * (uy * drx + ux * dry);
   }
   if constexpr ((VAR & kVarMrt) != 0) {
     // raw-moment MRT (eq. 7): raw moments of f = fbar + S/2 in the basis of
@@ -291,15 +377,15 @@ __device__ __forceinline__ int collide(C d[9], C drx, C dry, const Consts<C>& k,
   } else {
   // cascaded moment changes (Sec. 5); K background parts written out:
   // Kxx = rho0/3 + Kxx(dev), Kyy likewise, Kxxyy = rho0/9 + Kxxyy(dev)
-  const C r03 = k.rho0 * (C(1) / C(3));
-  const C g3 = k.w3 * (C(1) / C(12)) * (D3 - m3);
-  const C g4 = k.w4 * C(0.25) * (D4 - m4);
-  const C g5 = k.w5 * C(0.25) * (rho * uxy * k.ig - Kxy + D5);
-  const C g6 = k.w6 * C(0.25) * (k.third * rho * ux2 * uy + Kxxy - C(2) * ux * Kxy - uy * (r03 + Kxx)) -
+  const C r03 = k.r03;
+  const C g3 = k.q3 * (D3 - m3);
+  const C g4 = k.q4 * (D4 - m4);
+  const C g5 = k.q5 * (rho * uxy * k.ig - Kxy + D5);
+  const C g6 = k.q6 * (k.third * rho * ux2 * uy + Kxxy - C(2) * ux * Kxy - uy * (r03 + Kxx)) -
                C(0.5) * uy * (C(3) * g3 + g4) - C(2) * ux * g5;
-  const C g7 = k.w7 * C(0.25) * (k.third * rho * ux * uy2 + Kxyy - C(2) * uy * Kxy - ux * (r03 + Kyy)) -
+  const C g7 = k.q7 * (k.third * rho * ux * uy2 + Kxyy - C(2) * uy * Kxy - ux * (r03 + Kyy)) -
                C(0.5) * ux * (C(3) * g3 - g4) - C(2) * uy * g5;
-  const C g8 = k.w8 * C(0.25) *
+  const C g8 = k.q8 *
                    (drho * (C(1) / C(9)) + C(3) * rho * ux2 * uy2 -
                     (Kxxyy - C(2) * ux * Kxyy - C(2) * uy * Kxxy + ux2 * (r03 + Kyy) +
                      uy2 * (r03 + Kxx) + C(4) * uxy * Kxy)) -
@@ -336,16 +422,22 @@ __device__ __forceinline__ int collide(C d[9], C drx, C dry, const Consts<C>& k,
 }
 
 // ---------------------------------------------------------------------------
-// Streaming (eq. 2b) as a pull through the ghost frame: nine independent loads.
+// Streaming (eq. 2b) as a pull through the ghost frame: nine independent
+// loads, f_a(x - e_a) from plane a, all at the byte offset of node x.
 // ---------------------------------------------------------------------------
 template <class S>
 __device__ __forceinline__ void pull9(const typename S::T* __restrict__ fa, const Geom& g,
                                       const Consts<typename S::C>& k, int x, int y,
                                       typename S::C d[9]) {
-  const int own = gidx(g, x, y);
+  using T = typename S::T;
+  const uint32_t off = uint32_t(gidx(g, x, y)) * uint32_t(sizeof(T));
+  const Rsrc r = lattice_rsrc(fa);
 #pragma unroll
-  for (int a = 0; a < 9; ++a)
-    d[a] = S::dec(fa[a * g.plane + own - ex_of(a) - ey_of(a) * g.pitch], k.inv_scale);
+  for (int a = 0; a < 9; ++a) {
+    // plane a, shifted by -e_a; non-negative because a * plane > pitch + 1
+    const uint32_t so = uint32_t(a * g.plane - ex_of(a) - ey_of(a) * g.pitch) * uint32_t(sizeof(T));
+    d[a] = S::dec(Buf<T>::ld(r, off, so), k.inv_scale);
+  }
 }
 
 // Links of node (nx-1, y) that cross an OUTLET side (e_x = -1, source not a
@@ -421,64 +513,105 @@ __device__ __forceinline__ bool region_node(const Geom& g, const uint8_t* __rest
   return !(solid && solid[(long long)gy * g.nx + gx]);
 }
 
+// Bit masks over the velocity index of the links of node (x, y) whose source
+// lies beyond a non-periodic side (e_a points away from that side), and of
+// the populations that leave across a periodic side.
+__device__ __forceinline__ unsigned side_links(const Geom& g, int x, int y) {
+  const bool px = g.side[kW] == kPeriodic, py = g.side[kS] == kPeriodic;
+  unsigned m = 0;
+  if (!px && x == 0) m |= (1u << 1) | (1u << 5) | (1u << 8);
+  if (!px && x == g.nx - 1) m |= (1u << 3) | (1u << 6) | (1u << 7);
+  if (!py && y == 0) m |= (1u << 2) | (1u << 5) | (1u << 6);
+  if (!py && y == g.ny - 1) m |= (1u << 4) | (1u << 7) | (1u << 8);
+  return m;
+}
+__device__ __forceinline__ unsigned periodic_links(const Geom& g, int x, int y) {
+  const bool px = g.side[kW] == kPeriodic, py = g.side[kS] == kPeriodic;
+  unsigned m = 0;
+  if (px && x == 0) m |= (1u << 3) | (1u << 6) | (1u << 7);
+  if (px && x == g.nx - 1) m |= (1u << 1) | (1u << 5) | (1u << 8);
+  if (py && y == 0) m |= (1u << 4) | (1u << 7) | (1u << 8);
+  if (py && y == g.ny - 1) m |= (1u << 2) | (1u << 5) | (1u << 6);
+  return m;
+}
+
 // Boundary links owned by fluid node (x, y), written into the destination
 // lattice after its collision (post-collision deviations d):
-//  - half-way bounce-back (eq. 2b with a wall, lid or inlet at the source):
-//    the link alpha from a non-fluid source s = x - e_alpha is pulled next step
-//    from slot (s, alpha), which receives d_opp(alpha) plus the moving-wall
-//    term 6 w_alpha rho0 (e_alpha . u_w) (lid: tangential u_lid; inlet:
-//    parabolic profile at this node's y; corner links: stationary);
-//  - periodic sides: the population that leaves across a periodic side is
-//    copied to the frame slot its wrapped target pulls from.
-// nonfluid(a) tells whether the source of link a is solid or outside a
-// non-periodic side.
-template <class S, class NF>
+//  - half-way bounce-back (eq. 2b with a wall, lid, inlet or solid node at
+//    the source), for the links in bounce: the link alpha from a non-fluid
+//    source s = x - e_alpha is pulled next step from slot (s, alpha), which
+//    receives d_opp(alpha) plus the moving-wall term 6 w_alpha rho0
+//    (e_alpha . u_w) (lid: tangential u_lid; inlet: parabolic profile at this
+//    node's y; corner and solid sources: stationary).  That slot lies at the
+//    node's own offset shifted by -e_alpha in plane alpha, the offset the pull
+//    itself uses, so the store needs no per-lane address arithmetic;
+//  - periodic sides, for the populations in leave: the population that
+//    leaves across a periodic side is copied to the frame slot its wrapped
+//    target pulls from.
+// Every link test is uniform across the wavefront (wave_bounce, wave_leave:
+// the union over its lanes), so a wavefront only executes the links some lane
+// needs.
+template <class S>
 __device__ __forceinline__ void ghost_writes(typename S::T* __restrict__ fb, const Geom& g,
                                              const Consts<typename S::C>& k, int x, int y,
-                                             const typename S::C d[9], NF nonfluid) {
+                                             const typename S::C d[9], unsigned bounce,
+                                             unsigned leave, unsigned wave_bounce,
+                                             unsigned wave_leave) {
   using C = typename S::C;
+  using T = typename S::T;
   const bool px = g.side[kW] == kPeriodic, py = g.side[kS] == kPeriodic;
+  if (wave_bounce) {
+    const Rsrc r = lattice_rsrc(fb);
+    const uint32_t off = uint32_t(gidx(g, x, y)) * uint32_t(sizeof(T));
+    // kind of the side crossed in x and in y by this node's links
+    const int kx = x == 0 ? g.side[kW] : g.side[kE];
+    const int ky = y == 0 ? g.side[kS] : g.side[kN];
+    const C H = C(g.ny), yy = C(y) + C(0.5);
+    const C uin = C(4) * k.u_in_max * yy * (H - yy) * rcp(H * H);
 #pragma unroll
-  for (int a = 1; a < 9; ++a) {
-    const int ex = ex_of(a), ey = ey_of(a);
-    // bounce-back family
-    if (nonfluid(a)) {
-      const int sx = x - ex, sy = y - ey;
-      const bool xo = (sx < 0 || sx >= g.nx) && !px;
-      const bool yo = (sy < 0 || sy >= g.ny) && !py;
-      C corr = C(0);
-      bool write = true;
-      if (xo != yo) {
-        const int sd = xo ? (sx < 0 ? kW : kE) : (sy < 0 ? kS : kN);
-        const int kind = g.side[sd];
-        if (kind == kOutlet) {
-          write = false;
-        } else if (kind == kLid) {
-          const C uw = k.u_lid;
-          corr = C(6) * w_of<C>(a) * k.rho0 * ((sd == kS || sd == kN) ? C(ex) : C(ey)) * uw;
-        } else if (kind == kInlet) {
-          const C H = C(g.ny), yy = C(y) + C(0.5);
-          const C uin = C(4) * k.u_in_max * yy * (H - yy) / (H * H);
-          corr = C(6) * w_of<C>(a) * k.rho0 * C(ex) * uin;
-        }
-      }
-      if (write)
-        fb[a * g.plane + gidx(g, sx, sy)] = S::enc(d[opp_of(a)] + corr, k.scale);
-    }
-    // periodic copy
-    if (px || py) {
-      int tx = x + ex, ty = y + ey;
-      bool cross = false, valid = true;
-      if (tx < 0 || tx >= g.nx) {
-        if (px) { tx = tx < 0 ? tx + g.nx : tx - g.nx; cross = true; } else valid = false;
-      }
-      if (ty < 0 || ty >= g.ny) {
-        if (py) { ty = ty < 0 ? ty + g.ny : ty - g.ny; cross = true; } else valid = false;
-      }
-      if (cross && valid)
-        fb[a * g.plane + gidx(g, tx - ex, ty - ey)] = S::enc(d[a], k.scale);
+    for (int a = 1; a < 9; ++a) {
+      if (!((wave_bounce >> a) & 1u)) continue;
+      const int ex = ex_of(a), ey = ey_of(a);
+      const bool xo = !px && ((ex > 0 && x == 0) || (ex < 0 && x == g.nx - 1));
+      const bool yo = !py && ((ey > 0 && y == 0) || (ey < 0 && y == g.ny - 1));
+      const int kind = xo ? kx : ky;
+      const bool one = xo != yo;   // beyond exactly one side (else corner or solid)
+      const C uw = kind == kLid ? (yo ? C(ex) : C(ey)) * k.u_lid
+                                : (kind == kInlet ? C(ex) * uin : C(0));
+      const C corr = one ? C(6) * w_of<C>(a) * k.rho0 * uw : C(0);
+      const bool write = ((bounce >> a) & 1u) && !(one && kind == kOutlet);
+      const uint32_t so = uint32_t(a * g.plane - ex - ey * g.pitch) * uint32_t(sizeof(T));
+      if (write) Buf<T>::template st<0>(r, off, so, S::enc(d[opp_of(a)] + corr, k.scale));
     }
   }
+  if (wave_leave) {
+#pragma unroll
+    for (int a = 1; a < 9; ++a) {
+      if (!((wave_leave >> a) & 1u) || !((leave >> a) & 1u)) continue;
+      const int ex = ex_of(a), ey = ey_of(a);
+      int tx = x + ex, ty = y + ey;
+      bool valid = true;
+      if (tx < 0 || tx >= g.nx) {
+        if (px) tx = tx < 0 ? tx + g.nx : tx - g.nx;
+        else valid = false;
+      }
+      if (ty < 0 || ty >= g.ny) {
+        if (py) ty = ty < 0 ? ty + g.ny : ty - g.ny;
+        else valid = false;
+      }
+      if (valid) fb[(long long)a * g.plane + gidx(g, tx - ex, ty - ey)] = S::enc(d[a], k.scale);
+    }
+  }
+}
+
+// Union of a link mask over the active lanes of the wavefront (one ballot per
+// link; uniform result, inactive lanes contribute nothing).
+__device__ __forceinline__ unsigned wave_or(unsigned m) {
+  unsigned r = 0;
+#pragma unroll
+  for (int a = 1; a < 9; ++a)
+    if (__builtin_amdgcn_ballot_w64(((m >> a) & 1u) != 0) != 0) r |= 1u << a;
+  return r;
 }
 
 }  // namespace lbmk

@@ -62,6 +62,20 @@ inline Consts<C> make_consts(const lbm_params& p, double scale) {
   k.u_in_max = C(p.u_in_max);
   k.scale = C(scale);
   k.inv_scale = C(1.0 / scale);
+  const double h3 = 1.0 / p.omega3 - 0.5, h4 = 1.0 / w4 - 0.5, cg = 1.0 / g - 1.0;
+  k.q3 = C(p.omega3 / 12.0);
+  k.q4 = C(w4 / 4.0);
+  k.q5 = C(w4 / 4.0);
+  k.q6 = C(p.omega6 / 4.0);
+  k.q7 = C(p.omega7 / 4.0);
+  k.q8 = C(p.omega8 / 4.0);
+  k.cg3 = C(cg / 3.0);
+  k.l3 = C(2.0 / 3.0 * h3 * cg);
+  k.l4 = C(2.0 / 3.0 * h4 * cg);
+  k.l5 = C(1.0 / 3.0 * h4 * cg);
+  k.h5B = C(h4 * (1.0 / (g * g) - 1.0 / g));
+  k.d0 = C(-2.0 * (2.0 / (3.0 * p.omega3)) * (2.0 / (3.0 * w4)));
+  k.r03 = C(p.rho0 / 3.0);
   k.gi = p.gi_correct ? 1 : 0;
   k.force = (p.fx != 0.0 || p.fy != 0.0) ? 1 : 0;
   k.stencil = p.drho_stencil;
@@ -82,15 +96,26 @@ inline Geom make_geom_for(int nx, int ny, const int32_t side[4], size_t esize) {
   return g;
 }
 
+// One lattice (nine framed planes) is read and written through a single
+// buffer resource with 32-bit byte offsets, so it must hold fewer than 2^32
+// bytes at the given element size (FP32: up to about 10800^2 nodes).
+inline int check_lattice_bytes(int nx, int ny, size_t esize) {
+  const long long line = 128 / (long long)esize;
+  const long long pitch = ((nx + 3 * line) + line - 1) / line * line;   // upper bound
+  if (9LL * pitch * (ny + 2) * (long long)esize >= (1LL << 32))
+    return fail(LBM_EINVAL, "lattice too large for this storage (its nine framed planes must "
+                            "hold fewer than 2^32 bytes)");
+  return LBM_OK;
+}
+
 // Validation shared by lbm_create and lbm_batch_create.
 inline int validate(const lbm_grid* grid, const uint8_t* solid, const lbm_params* p) {
   if (!grid || !p) return fail(LBM_EINVAL, "null grid or params");
   if (grid->nx < 2 || grid->ny < 2) return fail(LBM_EINVAL, "nx and ny must be >= 2");
-  {
-    const long long pitch = grid->nx + 2 * 64 + 64;
-    if (9LL * pitch * (grid->ny + 2) >= (1LL << 31))
-      return fail(LBM_EINVAL, "lattice too large (9 framed planes must hold fewer than 2^31 "
-                              "elements)");
+  if (grid->nx > (1 << 30) || grid->ny > (1 << 30)) return fail(LBM_EINVAL, "lattice too large");
+  if (p->storage >= LBM_STORE_F64 && p->storage <= LBM_STORE_F16) {
+    const int rc = check_lattice_bytes(grid->nx, grid->ny, storage_bytes(p->storage));
+    if (rc) return rc;
   }
   for (int s = 0; s < 4; ++s)
     if (grid->side[s] < LBM_SIDE_PERIODIC || grid->side[s] > LBM_SIDE_OUTLET)

@@ -6,14 +6,18 @@
 // D2Q9 LBM for gfx950.
 //
 // Kernel layout.  A block is 64 x BY threads (BY wave64 wavefronts) and owns
-// one tile of 64 columns x (BY*R - 2) rows; each thread holds R consecutive
-// rows of one column.  The block's region adds one halo row above and below
-// (pulled by the first/last row of threads) and one halo column left and
-// right (pulled by lanes 0 and 63), so that the density gradient at the same
-// time level needs no second pass.  Phase 1 pulls the nine populations of
-// every region node through the ghost frame (nine independent coalesced
-// loads, no boundary logic), writes rho - rho0 to LDS (a sentinel for solid
-// or outside nodes) and keeps the populations in registers; after one
+// one tile of 64 columns x BY*R rows; each thread holds R consecutive rows of
+// one column.  The density gradient at the same time level needs rho on the
+// one-node ring around the tile too.  Phase 1 pulls the nine populations of
+// every tile node through the ghost frame (nine coalesced loads per row, all
+// at one per-lane byte offset: the direction's plane and streaming shift ride
+// in the scalar base of a buffer resource), keeps them in registers and writes
+// rho - rho0 to LDS (a sentinel for solid or outside nodes).  The ring costs
+// little: the first and the last wavefront pull the halo row above and below
+// the tile, and the two halo columns are loaded cooperatively, one population
+// per lane (16-lane groups, one group per halo node, nine lanes used), their
+// nine values summed across the group in the order of the per-node sum, so a
+// halo rho equals, bit for bit, the rho its own tile computes.  After one
 // barrier, phase 2 takes the density gradient from LDS, collides, stores the
 // nine populations with coalesced full-line stores and, on boundary nodes
 // only, writes the bounce-back and periodic values into the ghost/solid slots
@@ -21,7 +25,8 @@
 // extra work (non-equilibrium extrapolation from column nx-2).  Halo re-reads
 // are served by L2: one HBM read and one HBM write of each population per
 // step.  Tiles are mapped to blocks XCD by XCD so that neighbouring tiles
-// share an L2.
+// share an L2.  The finite-difference strain variant also needs the velocity
+// on the ring; there lanes 0 and 63 pull the halo columns node by node.
 //
 // Check steps also accumulate in FP64, per block, sum |u^{n+1}-u^n|^2,
 // sum |u^n|^2, sum (rho - rho0) and the guard count (wavefront shuffles, then
@@ -90,14 +95,14 @@ __device__ __forceinline__ void finish_node(typename S::T* __restrict__ fb, cons
                                             typename S::C ux, typename S::C uy, int guarded,
                                             double acc[4]) {
   using C = typename S::C;
+  using T = typename S::T;
   const Geom& g = args.g;
+  const uint32_t off = uint32_t(li) * uint32_t(sizeof(T));
+  const Rsrc r = lattice_rsrc(fb);
 #pragma unroll
-  for (int a = 0; a < 9; ++a) {
-    if constexpr (NTS)
-      __builtin_nontemporal_store(S::enc(d[a], k.scale), &fb[a * g.plane + li]);
-    else
-      fb[a * g.plane + li] = S::enc(d[a], k.scale);
-  }
+  for (int a = 0; a < 9; ++a)
+    Buf<T>::template st<NTS ? 2 : 0>(r, off, uint32_t(a * g.plane) * uint32_t(sizeof(T)),
+                                     S::enc(d[a], k.scale));
   C* ubuf = static_cast<C*>(args.ubuf);
   const int np = g.nx * g.ny;
   if (FL == kCheck) {
@@ -112,6 +117,35 @@ __device__ __forceinline__ void finish_node(typename S::T* __restrict__ fb, cons
     ubuf[fi] = ux;
     ubuf[np + fi] = uy;
   }
+}
+
+// Lane exchange inside rows of 16 lanes (DPP; lanes outside the row read 0).
+template <int CTRL>
+__device__ __forceinline__ float dpp_get(float v) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_get(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(unsigned(b)), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(unsigned(b >> 32)), CTRL, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, (unsigned long long)unsigned(lo) |
+                                        ((unsigned long long)unsigned(hi) << 32));
+}
+
+// Sum of lanes 0..8 of every 16-lane row (lanes 9..15 hold 0) into lane 0 of
+// the row, in the association of sum9: ((d0+d1)+(d2+d3)) + ((d4+d5)+(d6+d7))
+// + d8.  Steps: swap neighbours (quad_perm 1,0,3,2), swap pairs (quad_perm
+// 2,3,0,1), mirror the half-row (lane 0 takes lane 7, whose partial equals
+// lane 4's), shift the row by 8 (lane 0 takes lane 8 = d8).
+template <class C>
+__device__ __forceinline__ C row16_sum9(C v) {
+  v = v + dpp_get<0xB1>(v);
+  v = v + dpp_get<0x4E>(v);
+  v = v + dpp_get<0x141>(v);
+  v = v + dpp_get<0x108>(v);
+  return v;
 }
 
 // Check-step partials of one block: wavefront shuffles, then LDS.
@@ -129,6 +163,23 @@ __device__ __forceinline__ void block_partials(double acc[4], double (*s_red)[4]
     for (int i = 0; i < BY; ++i) t += s_red[i][lane];
     out[lane] = t;
   }
+}
+
+// Lattice column / row of a region coordinate: wrapped across a periodic
+// side, else mirrored onto the edge node across the half-way wall (the
+// region extends one node beyond the lattice; coordinates further out occur
+// only in ragged tiles, whose extra nodes feed no output).
+__device__ __forceinline__ int col_of(const Geom& g, int x) {
+  const bool px = g.side[kW] == kPeriodic;
+  if (x < 0) return px ? x + g.nx : 0;
+  if (x >= g.nx) return px ? (x - g.nx < g.nx ? x - g.nx : g.nx - 1) : g.nx - 1;
+  return x;
+}
+__device__ __forceinline__ int row_of(const Geom& g, int y) {
+  const bool py = g.side[kS] == kPeriodic;
+  if (y < 0) return py ? y + g.ny : 0;
+  if (y >= g.ny) return py ? (y - g.ny < g.ny ? y - g.ny : g.ny - 1) : g.ny - 1;
+  return y;
 }
 
 // Velocity of a pulled region node (gx, gy: its clamped lattice coordinates)
@@ -149,10 +200,15 @@ __device__ __forceinline__ void store_velocity(const C dd[9], bool on, int gx, i
 }
 
 // One tile of the fused step (the body of both the single-lattice kernel and
-// the persistent batch kernel).  LDS: s_rho[(BY*R + 2) * 66] of type C,
-// s_red[BY * 4]; with FDS (strain rates of the corrections by finite
-// differences of the velocity, VAR & kVarFds) also s_u, s_v of the size of
-// s_rho.  VAR & kVarMrt: the raw-moment MRT form of the collision.
+// the batch kernel).  LDS: s_rho[(BY*R + 2) * 66] of type C, s_red[BY * 4];
+// with FDS (strain rates of the corrections by finite differences of the
+// velocity, VAR & kVarFds) also s_u, s_v of the size of s_rho.
+// VAR & kVarMrt: the raw-moment MRT form of the collision.
+//
+// Region nodes beyond a non-periodic side hold the density of their mirror
+// image across the half-way wall (the clamped lattice node, the density-
+// gradient reading at the lattice sides), so only solid nodes carry the
+// sentinel (their density is replaced by the differentiating node's own).
 template <class S, int BY, int R, int FL, bool OBST, bool OUTL, int VAR = 0, bool INT = false>
 __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
                                           typename S::T* __restrict__ fb, const StepArgs& args,
@@ -166,7 +222,7 @@ __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
   constexpr int RO = BY * R;   // output rows of the tile
   constexpr int RR = RO + 2;   // region rows (one halo row above and below)
   constexpr int W = kLanes + 2;
-  const C SENT = C(HUGE_VALF);
+  const C SENT = C(HUGE_VALF);   // LDS value of a solid region node
   const Geom& g = args.g;
   const int lane = threadIdx.x;
   const int w = threadIdx.y;
@@ -175,84 +231,159 @@ __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
   const int x = tx * kLanes + lane;
   const int ytile = ty * RO;        // first output row of the tile
   const int y0 = ytile + w * R;     // this thread's first row
-  const bool halo_lane = lane == 0 || lane == kLanes - 1;
-  const int hx = lane == 0 ? x - 1 : x + 1;
-  const int hc = lane == 0 ? 0 : W - 1;
   const C* hist_in = static_cast<const C*>(args.hist_in);
   const C* force = static_cast<const C*>(args.force);
   const bool has_force = args.has_force != 0;
+  const int x0 = tx * kLanes;       // first column of the tile
 
-
-  // rho - rho0 of one region row (main lane and, on lanes 0/63, the halo
-  // column) into LDS row lr; used for the two halo rows
-  auto halo_row = [&](int y, int lr) {
-    int gx, gy, hgx, hgy;
-    bool ok = region_coords(g, x, y, gx, gy) || INT;
-    bool hok = halo_lane && (region_coords(g, hx, y, hgx, hgy) || INT);
-    C dm[9], dh[9];
-    pull9<S>(fa, g, k, gx, gy, dm);
-    if (halo_lane) pull9<S>(fa, g, k, hgx, hgy, dh);
-    if (OBST) {
-      ok = ok && !args.solid[gy * g.nx + gx];
-      if (halo_lane) hok = hok && !args.solid[hgy * g.nx + hgx];
-    }
-    if (OUTL) {
-      C a_, b_;
-      if (ok && gx == g.nx - 1) outlet_links<S>(fa, g, k, has_force, force, hist_in, gy, dm, a_, b_);
-      if (hok && hgx == g.nx - 1) outlet_links<S>(fa, g, k, has_force, force, hist_in, hgy, dh, a_, b_);
-    }
-    s_rho[lr][lane + 1] = ok ? sum9<C>(dm) : SENT;
-    if (halo_lane) s_rho[lr][hc] = hok ? sum9<C>(dh) : SENT;
-    if (FDS) {
-      store_velocity<C>(dm, ok, gx, gy, k, has_force, force, g, s_u[lr][lane + 1],
-                        s_v[lr][lane + 1]);
-      if (halo_lane)
-        store_velocity<C>(dh, hok, hgx, hgy, k, has_force, force, g, s_u[lr][hc], s_v[lr][hc]);
-    }
-  };
-
-  // ---- phase 1: one batch of loads per row (main node, halo column, mask),
-  // then rho - rho0 to LDS (sentinel for solid / outside nodes).  The first
-  // and the last wavefront also pull the halo rows.
-  C d[R][9], dh[R][9];
+  // ---- phase 1: every load of the tile is issued before any is used (one
+  // memory round trip per wavefront): the own rows (nine loads per row, plus
+  // the mask), the halo row of the first / last wavefront, and the
+  // cooperative halo-column loads.  Then rho - rho0 to LDS.
+  static_assert(BY >= 2, "the first and the last wavefront each pull one halo row");
+  // lattice coordinates of the region nodes: the lane's column (per lane),
+  // every row (uniform), the two halo columns (uniform)
+  const int gx = INT ? x : col_of(g, x);
+  C d[R][9];
   C us[R], vs[R];
-  bool ok[R], hok[R];
-  int gxr[R], gyr[R], hgx[R], hgy[R];
+  bool sol[R];
+  int gyr[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int y = y0 + r;
-    ok[r] = region_coords(g, x, y, gxr[r], gyr[r]) || INT;
-    hok[r] = halo_lane && (region_coords(g, hx, y, hgx[r], hgy[r]) || INT);
-    pull9<S>(fa, g, k, gxr[r], gyr[r], d[r]);
-    if (halo_lane) pull9<S>(fa, g, k, hgx[r], hgy[r], dh[r]);
-    if (OBST) {
-      ok[r] = ok[r] && !args.solid[gyr[r] * g.nx + gxr[r]];
-      if (halo_lane) hok[r] = hok[r] && !args.solid[hgy[r] * g.nx + hgx[r]];
+    gyr[r] = INT ? y0 + r : row_of(g, y0 + r);
+    pull9<S>(fa, g, k, gx, gyr[r], d[r]);
+    sol[r] = OBST && args.solid[gyr[r] * g.nx + gx];
+  }
+  // halo row: above the tile for wavefront 0, below it for the last one
+  const bool row_wave = w == 0 || w == BY - 1;
+  const int hy = w == 0 ? ytile - 1 : ytile + RO;
+  const int hlr = w == 0 ? 0 : RR - 1;
+  const int hgy = INT ? hy : row_of(g, hy);
+  C dm[9];
+  bool hrsol = false;
+  if (row_wave) {
+    pull9<S>(fa, g, k, gx, hgy, dm);
+    hrsol = OBST && args.solid[hgy * g.nx + gx];
+  }
+
+  // Region rows whose two halo-column nodes this wavefront provides: its own
+  // R rows, and the halo row it pulled (corner nodes).  q-th such row: LDS row
+  // and lattice row.
+  const int nh = R + (row_wave ? 1 : 0);
+  auto halo_rowof = [&](int q, int& lr) {
+    if (q < R) {
+      lr = w * R + q + 1;
+      return gyr[q];
+    }
+    lr = hlr;
+    return hgy;
+  };
+  const int hxl = INT ? x0 - 1 : col_of(g, x0 - 1);
+  const int hxr = INT ? x0 + kLanes : col_of(g, x0 + kLanes);
+  // A right halo column on (or mirrored onto) the OUTLET column needs the
+  // outlet links of its nodes; lane 63 then pulls it node by node (the left
+  // column stays cooperative), as the finite-difference variant does for both
+  // columns.
+  const bool lane_halo = FDS || (OUTL && x0 + kLanes >= g.nx - 1);
+  // cooperative halo columns: 16-lane group gr takes pair p = 4 i + gr
+  // (region row p / 2, left or right column p % 2), lane sub of the group
+  // loads population sub of that node
+  constexpr int kHC = (2 * (R + 1) + 3) / 4;
+  const int sub = lane & 15, gr = lane >> 4;
+  C hc[kHC];
+  bool hcsol[kHC];
+  int hclr[kHC];
+  if (!FDS) {
+    // the halo loads go through a pointer the compiler may not assume
+    // unaliased, so the memory barrier below keeps them ahead of the LDS work
+    using GT = const __attribute__((address_space(1))) typename S::T;
+    const typename S::T* fl = uniform_ptr(fa);
+    asm volatile("" : "+s"(fl));
+    GT* fh = (GT*)fl;
+    // e_a of a lane-dependent direction a, from 2-bit fields (e + 1) per
+    // direction (no divergent selects)
+    const int a = sub < 9 ? sub : 0;
+    const int aex = int((0x20919u >> (2 * a)) & 3u) - 1;
+    const int aey = int((0x02865u >> (2 * a)) & 3u) - 1;
+#pragma unroll
+    for (int i = 0; i < kHC; ++i) {
+      const int p = 4 * i + gr;
+      const bool act = p < 2 * nh;
+      const int cy = halo_rowof(act ? (p >> 1) : 0, hclr[i]);
+      const int cx = (p & 1) ? hxr : hxl;
+      const long long li =
+          (long long)a * g.plane + gidx(g, cx, cy) - aex - (long long)aey * g.pitch;
+      hc[i] = S::dec(fh[li], k.inv_scale);
+      hcsol[i] = OBST && args.solid[cy * g.nx + cx];
+      if (!act || sub >= 9) hc[i] = C(0);
     }
   }
-  if (w == 0) halo_row(ytile - 1, 0);
-  if (w == BY - 1) halo_row(ytile + RO, RR - 1);
+
+  // every load above is issued before anything below consumes one (keeps
+  // the compiler from interleaving the LDS writes with the halo loads, which
+  // would cost one memory round trip per group of loads)
+  __builtin_amdgcn_sched_barrier(0);
+  asm volatile("" ::: "memory");
+
+  // a node on the outlet column completes its links (non-equilibrium
+  // extrapolation from column nx - 2); so does a region node mirrored onto it
   if (OUTL) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      if (ok[r] && gxr[r] == g.nx - 1) outlet_links<S>(fa, g, k, has_force, force, hist_in, gyr[r], d[r], us[r], vs[r]);
-      if (hok[r] && hgx[r] == g.nx - 1) {
-        C a_, b_;
-        outlet_links<S>(fa, g, k, has_force, force, hist_in, hgy[r], dh[r], a_, b_);
-      }
+    for (int r = 0; r < R; ++r)
+      if (!sol[r] && gx == g.nx - 1)
+        outlet_links<S>(fa, g, k, has_force, force, hist_in, gyr[r], d[r], us[r], vs[r]);
+    if (row_wave && !hrsol && gx == g.nx - 1) {
+      C a_, b_;
+      outlet_links<S>(fa, g, k, has_force, force, hist_in, hgy, dm, a_, b_);
     }
   }
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    s_rho[w * R + r + 1][lane + 1] = ok[r] ? sum9<C>(d[r]) : SENT;
-    if (halo_lane) s_rho[w * R + r + 1][hc] = hok[r] ? sum9<C>(dh[r]) : SENT;
+    s_rho[w * R + r + 1][lane + 1] = sol[r] ? SENT : sum9<C>(d[r]);
     if (FDS) {
       const int lr = w * R + r + 1;
-      store_velocity<C>(d[r], ok[r], gxr[r], gyr[r], k, has_force, force, g, s_u[lr][lane + 1],
+      store_velocity<C>(d[r], !sol[r], gx, gyr[r], k, has_force, force, g, s_u[lr][lane + 1],
                         s_v[lr][lane + 1]);
-      if (halo_lane)
-        store_velocity<C>(dh[r], hok[r], hgx[r], hgy[r], k, has_force, force, g, s_u[lr][hc],
-                          s_v[lr][hc]);
+    }
+  }
+  if (row_wave) {
+    s_rho[hlr][lane + 1] = hrsol ? SENT : sum9<C>(dm);
+    if (FDS)
+      store_velocity<C>(dm, !hrsol, gx, hgy, k, has_force, force, g, s_u[hlr][lane + 1],
+                        s_v[hlr][lane + 1]);
+  }
+  if (!FDS) {
+    // both columns, or the left one when lane 63 pulls the right one
+    const unsigned cols = lane_halo ? 1u : 3u;
+#pragma unroll
+    for (int i = 0; i < kHC; ++i) {
+      if (4 * i >= 2 * nh) break;
+      const int p = 4 * i + gr;
+      const C v = row16_sum9<C>(hc[i]);
+      if (p < 2 * nh && sub == 0 && ((cols >> (p & 1)) & 1u))
+        s_rho[hclr[i]][(p & 1) ? W - 1 : 0] = hcsol[i] ? SENT : v;
+    }
+  }
+  if (lane_halo) {
+    const bool halo_lane = FDS ? (lane == 0 || lane == kLanes - 1) : lane == kLanes - 1;
+    const int hcol = lane == 0 ? 0 : W - 1;
+    for (int q = 0; q < nh; ++q) {
+      int lr;
+      const int qgy = halo_rowof(q, lr);
+      if (halo_lane) {
+        const int qgx = lane == 0 ? hxl : hxr;
+        C dq[9];
+        pull9<S>(fa, g, k, qgx, qgy, dq);
+        const bool qsol = OBST && args.solid[qgy * g.nx + qgx];
+        if (OUTL && !qsol && qgx == g.nx - 1) {
+          C a_, b_;
+          outlet_links<S>(fa, g, k, has_force, force, hist_in, qgy, dq, a_, b_);
+        }
+        s_rho[lr][hcol] = qsol ? SENT : sum9<C>(dq);
+        if (FDS)
+          store_velocity<C>(dq, !qsol, qgx, qgy, k, has_force, force, g, s_u[lr][hcol],
+                            s_v[lr][hcol]);
+      }
     }
   }
   __syncthreads();
@@ -263,16 +394,16 @@ __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
   for (int r = 0; r < R; ++r) {
     const int ry = w * R + r + 1;  // LDS row
     const int y = y0 + r;
-    if (x >= g.nx || y >= g.ny) continue;
+    if (!INT && (x >= g.nx || y >= g.ny)) continue;
     const int c = lane + 1;
-    const C own = s_rho[ry][c];
-    if (!INT && own == SENT) continue;  // solid node
-    // the eight neighbours, sentinel = solid or outside a non-periodic side
+    // the eight neighbours (sentinel = solid node)
     const C nE = s_rho[ry][c + 1], nW = s_rho[ry][c - 1];
     const C nN = s_rho[ry + 1][c], nS = s_rho[ry - 1][c];
     const C nNE = s_rho[ry + 1][c + 1], nNW = s_rho[ry + 1][c - 1];
     const C nSE = s_rho[ry - 1][c + 1], nSW = s_rho[ry - 1][c - 1];
-    auto sub = [&](C v) { return (!INT && v == SENT) ? own : v; };
+    const C own = s_rho[ry][c];
+    if (OBST && !INT && own == SENT) continue;  // solid node
+    auto sub = [&](C v) { return (OBST && !INT && v == SENT) ? own : v; };
     C drx, dry;
     if (k.stencil == 0) {
       // isotropic: d rho = 3 sum_a w_a e_a rho(x + e_a)
@@ -309,19 +440,23 @@ __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
     const int gd = collide<C, VAR>(d[r], drx, dry, k, fx, fy, drho, ux, uy, sxx, syy);
     finish_node<S, FL, (VAR & kVarNts) != 0>(fb, args, k, d[r], gidx(g, x, y), y * g.nx + x, drho, ux, uy,
                        gd, acc);
-    // boundary links: source of link a is the neighbour at -e_a
-    const bool any_nf = (nE == SENT) | (nW == SENT) | (nN == SENT) | (nS == SENT) |
-                        (nNE == SENT) | (nNW == SENT) | (nSE == SENT) | (nSW == SENT);
-    const bool edge = x == 0 || x == g.nx - 1 || y == 0 || y == g.ny - 1;
-    if (!INT && (any_nf || edge)) {
-      auto nonfluid = [&](int a) {
-        const int sx = -ex_of(a), sy = -ey_of(a);
-        const C v = sy == 0 ? (sx > 0 ? nE : nW)
-                            : (sy > 0 ? (sx > 0 ? nNE : (sx < 0 ? nNW : nN))
-                                      : (sx > 0 ? nSE : (sx < 0 ? nSW : nS)));
-        return v == SENT;
-      };
-      ghost_writes<S>(fb, g, k, x, y, d[r], nonfluid);
+    // boundary links: the source of link a (the neighbour at -e_a) lies
+    // beyond a non-periodic side or is a solid node; populations leaving
+    // across a periodic side
+    // a wavefront touches a side only in the first / last tile column or on
+    // the first / last lattice row (uniform test)
+    const bool side_wave = x0 == 0 || x0 + kLanes >= g.nx || y == 0 || y == g.ny - 1;
+    if (!INT && (side_wave || OBST)) {
+      unsigned bounce = side_links(g, x, y);
+      if (OBST) {
+        bounce |= (nW == SENT ? 1u << 1 : 0u) | (nS == SENT ? 1u << 2 : 0u) |
+                  (nE == SENT ? 1u << 3 : 0u) | (nN == SENT ? 1u << 4 : 0u) |
+                  (nSW == SENT ? 1u << 5 : 0u) | (nSE == SENT ? 1u << 6 : 0u) |
+                  (nNE == SENT ? 1u << 7 : 0u) | (nNW == SENT ? 1u << 8 : 0u);
+      }
+      const unsigned leave = periodic_links(g, x, y);
+      const unsigned wb = wave_or(bounce), wl = wave_or(leave);
+      if (wb | wl) ghost_writes<S>(fb, g, k, x, y, d[r], bounce, leave, wb, wl);
     }
     if (OUTL && x == g.nx - 1) {
       C* ho = static_cast<C*>(args.hist_out);
@@ -360,19 +495,15 @@ __global__ __launch_bounds__(kLanes* BY) void step_kernel(const typename S::T* _
                                            s_uv[FDS ? 1 : 0]);
 }
 
-// One fused step over all tiles (one block per tile).  var selects the
-// instantiation (kVarFds: strain rates from finite differences of the
-// velocity; kVarMrt: raw-moment MRT collision); it is passed here rather than
-// in the constants because the kernel-argument layout of the default step is
-// kept as it is (one more word in Consts re-packs its scalar loads and costs
-// about 3 %).
-void launch_step_f64(int by, int rows, int flavor, int var, const void* src, void* dst,
-                     const StepArgs& a, const Consts<double>& k, hipStream_t st);
-void launch_step_f32(int by, int rows, int flavor, int var, const void* src, void* dst,
-                     const StepArgs& a, const Consts<float>& k, hipStream_t st);
-void launch_step_bf16(int by, int rows, int flavor, int var, const void* src, void* dst,
-                     const StepArgs& a, const Consts<float>& k, hipStream_t st);
-void launch_step_f16(int by, int rows, int flavor, int var, const void* src, void* dst,
-                     const StepArgs& a, const Consts<float>& k, hipStream_t st);
+// One fused step over all tiles (one block per tile) for storage code ST
+// (LBM_STORE_*) and flavour FL; consts points to the Consts of the storage's
+// compute type.  var selects the instantiation (kVarFds: strain rates from
+// finite differences of the velocity; kVarMrt: raw-moment MRT collision;
+// kVarNts: non-temporal population stores); it is passed here rather than in
+// the constants so that the kernel-argument layout of the default step stays
+// as small as it is.  Defined in lbm_step.hip, compiled once per (ST, FL).
+template <int ST, int FL>
+void launch_step(int by, int rows, int var, const void* src, void* dst, const StepArgs& a,
+                 const void* consts, hipStream_t st);
 
 }  // namespace lbmk

@@ -68,6 +68,17 @@ def test_invalid_configurations_are_rejected(lib, kw, sides):
     assert L.lbm_last_error()
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_lattices_over_4_gib_are_rejected(lib, storage):
+    """One lattice is addressed with 32-bit byte offsets: 12000^2 nodes need
+    5.3 GB in FP32 (nine framed planes) and are refused before any device
+    work."""
+    lbm, L = lib
+    rc = _create(L, lbm, nx=12000, ny=12000, storage=storage)
+    assert rc == lbm.LBM_EINVAL
+    assert b"2^32 bytes" in L.lbm_last_error()
+
+
 def test_all_solid_mask_is_rejected(lib):
     lbm, L = lib
     assert _create(L, lbm, mask=np.ones((16, 16))) == lbm.LBM_EINVAL

@@ -282,6 +282,23 @@ def test_lattices_beyond_the_infinity_cache_against_oracle(lbm):
     assert err <= 1e-11
 
 
+@pytest.mark.parametrize("storage,tol", [("bf16", 3e-2), ("f16", 3e-3)])
+def test_16bit_lattices_beyond_the_infinity_cache_against_oracle(lbm, storage, tol):
+    """The 16-bit storages also switch to non-temporal population stores when
+    the two lattices exceed 256 MiB (3072 x 2560: 283 MiB): all nodes after
+    20 steps against the oracle, with the bounds of the small 16-bit test."""
+    nx, ny, U = 3072, 2560, 0.1
+    _say(f"{nx}x{ny} {storage} cavity 20 steps (non-temporal stores)")
+    o, g = run_pair(lbm, nx, ny, cavity_sides(), 20, storage=storage, check_every=10,
+                    nu=U * nx / 1000, gamma=0.5, u_lid=U)
+    _, uxo, uyo = o.fields()
+    _, uxg, uyg = g.fields()
+    g.close()
+    err = max(np.abs(uxg - uxo).max(), np.abs(uyg - uyo).max()) / U
+    _say("max|du|/U", err)
+    assert err < tol
+
+
 @pytest.mark.parametrize("gamma", [1.0, 0.5])
 def test_gi_shear_wave_2048_full_size(lbm, gamma):
     """Full-size GI check (2048^2 periodic, a = 1e-3, m = 16): with the

@@ -1,8 +1,9 @@
 """Pins of the oracle's density-gradient step (Sec. 5: an isotropic finite
 difference of rho at the same time level; central differences as the
 alternative) and of its neighbour rule at walls, lids, solid nodes and
-periodic sides (reading R7: a neighbour that is solid or lies beyond a
-non-periodic side contributes the node's own value; periodic sides wrap).
+periodic sides (reading R7: a neighbour beyond a non-periodic side takes
+the value of its mirror image across the half-way wall; a solid neighbour
+contributes the node's own value; periodic sides wrap).
 
 Every expected value below comes from mathematics the stencil must satisfy
 (exactness on quadratic fields, the closed-form response to a sampled sine)
@@ -74,19 +75,22 @@ def test_gradient_wraps_periodic_sides(oracle_lib, stencil):
 
 @pytest.mark.parametrize("sides", [cavity_sides(), [WALL, LID, LID, WALL]])
 def test_gradient_at_walls_and_lids_hand_values(oracle_lib, sides):
-    """R7 at non-periodic sides, whatever their kind (wall or lid): the
-    missing neighbours take the node's own value.  For the linear field
-    q = i + 2 j on a 4 x 3 lattice:
+    """R7 at non-periodic sides, whatever their kind (wall or lid): the walls
+    lie half-way, so a neighbour beyond a side takes the value of its mirror
+    image across the wall, the node on the lattice edge.  For the linear
+    field q = i + 2 j on a 4 x 3 lattice:
 
     isotropic, interior node (1, 1): exact, (1, 2).
-    isotropic, corner (0, 0), q = 0: the neighbours E, N, NE are inside
-      (q = 1, 2, 3); W, S, NW, SW, SE are outside and read 0, so
-      gx = (1 - 0)/3 + ((3 - 0) + (0 - 0))/12 = 1/3 + 1/4 = 7/12,
-      gy = (2 - 0)/3 + ((3 - 0) + (0 - 0))/12 = 2/3 + 1/4 = 11/12.
-    isotropic, top edge (1, 2), q = 5: N, NE, NW outside (read 5);
-      E = 6, W = 4, S = 3, SE = 4, SW = 2, so
-      gx = (6 - 4)/3 + ((5 - 5) + (4 - 2))/12 = 2/3 + 1/6 = 5/6,
-      gy = (5 - 3)/3 + ((5 - 4) + (5 - 2))/12 = 2/3 + 1/3 = 1.
+    isotropic, corner (0, 0), q = 0: E, N, NE are inside (q = 1, 2, 3); the
+      mirrors give W -> (0, 0) = 0, S -> (0, 0) = 0, SW -> (0, 0) = 0,
+      NW -> (0, 1) = 2, SE -> (1, 0) = 1, so
+      gx = (1 - 0)/3 + ((3 - 2) + (1 - 0))/12 = 1/3 + 1/6 = 1/2,
+      gy = (2 - 0)/3 + ((3 - 1) + (2 - 0))/12 = 2/3 + 1/3 = 1.
+    isotropic, top edge (1, 2), q = 5: the mirrors give N -> (1, 2) = 5,
+      NE -> (2, 2) = 6, NW -> (0, 2) = 4; E = 6, W = 4, S = 3, SE = 4, SW = 2:
+      gx = (6 - 4)/3 + ((6 - 4) + (4 - 2))/12 = 2/3 + 1/3 = 1,
+      gy = (5 - 3)/3 + ((6 - 4) + (4 - 2))/12 = 2/3 + 1/3 = 1.
+    The derivative along a wall stays exact; across it, half the slope.
     central, corner (0, 0): gx = (1 - 0)/2 = 1/2, gy = (2 - 0)/2 = 1.
     central, top edge (1, 2): gx = (6 - 4)/2 = 1, gy = (5 - 3)/2 = 1.
     """
@@ -96,14 +100,33 @@ def test_gradient_at_walls_and_lids_hand_values(oracle_lib, sides):
     o = _lattice(nx, ny, sides, 0)
     gx, gy = o.fd_gradient(q)
     assert gx[1, 1] == pytest.approx(1.0, abs=1e-15) and gy[1, 1] == pytest.approx(2.0, abs=1e-15)
-    assert gx[0, 0] == pytest.approx(7 / 12, abs=1e-15)
-    assert gy[0, 0] == pytest.approx(11 / 12, abs=1e-15)
-    assert gx[2, 1] == pytest.approx(5 / 6, abs=1e-15)
+    assert gx[0, 0] == pytest.approx(0.5, abs=1e-15)
+    assert gy[0, 0] == pytest.approx(1.0, abs=1e-15)
+    assert gx[2, 1] == pytest.approx(1.0, abs=1e-15)
     assert gy[2, 1] == pytest.approx(1.0, abs=1e-15)
     o = _lattice(nx, ny, sides, 1)
     gx, gy = o.fd_gradient(q)
     assert gx[0, 0] == pytest.approx(0.5, abs=1e-15) and gy[0, 0] == pytest.approx(1.0, abs=1e-15)
     assert gx[2, 1] == pytest.approx(1.0, abs=1e-15) and gy[2, 1] == pytest.approx(1.0, abs=1e-15)
+
+
+def test_gradient_mirror_next_to_a_solid_edge_node(oracle_lib):
+    """A mirror image that is itself solid falls back to the node's own value:
+    on a 4 x 3 cavity with the edge node (0, 2) solid and q = i + 2 j, node
+    (1, 2) sees W = (0, 2) solid -> own 5, NW beyond the N wall -> mirror
+    (0, 2), solid -> own 5, N -> mirror (1, 2) = 5, NE -> mirror (2, 2) = 6,
+    E = 6, S = 3, SE = 4, SW = 2:
+      gx = (6 - 5)/3 + ((6 - 5) + (4 - 2))/12 = 1/3 + 1/4 = 7/12,
+      gy = (5 - 3)/3 + ((6 - 4) + (5 - 2))/12 = 2/3 + 5/12 = 13/12."""
+    nx, ny = 4, 3
+    J, I = np.mgrid[0:ny, 0:nx]
+    q = (I + 2 * J).astype(float)
+    solid = np.zeros((ny, nx), np.uint8)
+    solid[2, 0] = 1
+    o = _lattice(nx, ny, cavity_sides(), 0, solid=solid)
+    gx, gy = o.fd_gradient(q)
+    assert gx[2, 1] == pytest.approx(7 / 12, abs=1e-15)
+    assert gy[2, 1] == pytest.approx(13 / 12, abs=1e-15)
 
 
 def test_gradient_next_to_a_solid_node_hand_values(oracle_lib):
