@@ -176,6 +176,19 @@ int lbm_fields(lbm_ctx* ctx, double* rho, double* ux, double* uy);
 /* Same into device arrays of ny*nx floats.  Synchronises. */
 int lbm_fields_device(lbm_ctx* ctx, float* rho, float* ux, float* uy);
 
+/* lbm_fields for callers that cannot allocate device memory (code running
+ * under graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * same values into the same caller-owned host arrays, staged through a
+ * fixed 3 MiB device array of the library (one per GPU, 131072 nodes per
+ * chunk of whole rows) instead of a per-call allocation; no hipMalloc or
+ * hipFree.  The staging array is shared by every call on a GPU and keeps
+ * the last call's contents: calls that overlap on one GPU (several threads,
+ * or contexts on different streams) race for it and must be serialised by
+ * the caller.  Synchronises the context's stream.  Errors: LBM_EINVAL for a
+ * null context or rows longer than 131072 nodes; LBM_EDEVICE when a HIP
+ * call fails. */
+int lbm_fields_noalloc(lbm_ctx* ctx, double* rho, double* ux, double* uy);
+
 /* Current post-collision populations f (not deviations), decoded to FP64,
  * into a caller-owned host array of 9*ny*nx doubles.  Synchronises. */
 int lbm_populations(lbm_ctx* ctx, double* f);

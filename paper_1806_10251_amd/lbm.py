@@ -31,7 +31,7 @@ EXPORTS = (
     "lbm_batch_residual", "lbm_batch_fields", "lbm_batch_set_launch", "lbm_batch_destroy",
     "lbm_set_storage", "lbm_batch_set_plateau", "lbm_batch_status", "lbm_batch_set_enabled",
     "lbm_batch_set_storage", "lbm_average_last_two", "lbm_batch_average_last_two",
-    "lbm_set_force_field",
+    "lbm_set_force_field", "lbm_fields_noalloc",
 )
 
 
@@ -85,6 +85,7 @@ def load():
         "lbm_guard_count": [vp, P(i64)],
         "lbm_steps": [vp, P(i64)],
         "lbm_fields": [vp, vp, vp, vp],
+        "lbm_fields_noalloc": [vp, vp, vp, vp],
         "lbm_fields_device": [vp, vp, vp, vp],
         "lbm_populations": [vp, vp],
         "lbm_save": [vp, ctypes.c_char_p],
@@ -257,6 +258,15 @@ class Lattice:
     def fields(self):
         out = [np.zeros((self.ny, self.nx)) for _ in range(3)]
         _check(load().lbm_fields(self._h, *[o.ctypes.data_as(ctypes.c_void_p) for o in out]))
+        return tuple(out)
+
+    def fields_noalloc(self, rho=True, ux=True, uy=True):
+        """fields() through the entry point that allocates no device memory
+        (a fixed per-GPU staging array; concurrent calls on one GPU race).
+        Unrequested fields come back as None."""
+        out = [np.zeros((self.ny, self.nx)) if w else None for w in (rho, ux, uy)]
+        ptr = [o.ctypes.data_as(ctypes.c_void_p) if o is not None else None for o in out]
+        _check(load().lbm_fields_noalloc(self._h, *ptr))
         return tuple(out)
 
     def fields_device(self, rho=None, ux=None, uy=None):
