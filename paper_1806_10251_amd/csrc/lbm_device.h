@@ -177,6 +177,10 @@ struct Consts {
   int stencil;           // 0 isotropic, 1 central
 };
 
+// Integer switches of the constants, read as wave-uniform values whether the
+// constants sit in scalar registers or in LDS.
+__device__ __forceinline__ int uflag(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 // Lattice geometry and storage layout.  Each population plane holds the
 // lattice inside a one-node ghost frame (x = -1 .. nx, y = -1 .. ny); rows are
 // padded so that column 0 of every row starts a 128-byte line.  Ghost and
@@ -184,11 +188,15 @@ struct Consts {
 // node that owns them; see ghost_writes), so the pull itself is uniform.
 struct Geom {
   int nx, ny;
-  int side[4];
+  int sides;        // kind of side s (kW, kE, kS, kN) in bits 4s .. 4s + 3
   int pitch;        // stored elements per row
   int padx;         // offset of column 0 within a stored row
-  int plane;  // pitch * (ny + 2); 9 * plane < 2^31
+  int plane;        // pitch * (ny + 2); nine planes hold fewer than 2^32 bytes
 };
+
+__host__ __device__ __forceinline__ int side_of(const Geom& g, int s) {
+  return (g.sides >> (4 * s)) & 15;
+}
 
 // Element offsets within a plane and across the nine planes fit in 32 bits
 // (enforced at creation), so loads and stores use a 64-bit base plus a
@@ -247,7 +255,7 @@ __device__ __forceinline__ void macro(const C d[9], const Consts<C>& k, C fx, C 
   drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
   C jx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
   C jy = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
-  if (k.force) {
+  if (uflag(k.force)) {
     jx += C(0.5) * fx * k.ig;
     jy += C(0.5) * fy * k.ig;
   }
@@ -284,7 +292,7 @@ __device__ __forceinline__ int collide(C d[9], C drx, C dry, const Consts<C>& k,
   C Kxxy = s56 - s78;
   C Kxyy = (d[5] - d[6]) - (d[7] - d[8]);
   C Kxxyy = s56 + s78;
-  if (k.force) {
+  if (uflag(k.force)) {
     jx += C(0.5) * fx * k.ig;
     jy += C(0.5) * fy * k.ig;
   }
@@ -294,7 +302,7 @@ __device__ __forceinline__ int collide(C d[9], C drx, C dry, const Consts<C>& k,
   const C ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
   // source raw moments sigma' (Sec. 3); moments below are those of f = fbar + S/2
   C s[9];
-  if (k.force) {
+  if (uflag(k.force)) {
     const C ig2 = k.ig * k.ig;
     s[0] = C(0);
     s[1] = fx * k.ig;
@@ -318,7 +326,7 @@ __device__ __forceinline__ int collide(C d[9], C drx, C dry, const Consts<C>& k,
 
   C D3 = C(0), D4 = C(0), D5 = C(0);
   int guarded = 0;
-  if (k.gi) {
+  if (uflag(k.gi)) {
     const C Aux2 = k.A * ux2, Auy2 = k.A * uy2, Bux2 = k.B * ux2, Buy2 = k.B * uy2;
     // local strain rates from the 2x2 system of eqs. 51-53 (eq. 55, sign of
     // the c~1 term as given by Cramer's rule)
@@ -403,7 +411,7 @@ __device__ __forceinline__ int collide(C d[9], C drx, C dry, const Consts<C>& k,
   d[7] += t2g3 + g5 + g6 + g7 + g8;
   d[8] += t2g3 - g5 + g6 - g7 + g8;
   }
-  if (k.force) {
+  if (uflag(k.force)) {
     // S = inverse raw-moment map of sigma'
     d[0] += s[0] - s[3] - s[4] + s[8];
     d[1] += C(0.5) * (s[1] + s[3] - s[7] - s[8]);
@@ -444,7 +452,7 @@ __device__ __forceinline__ void pull9(const typename S::T* __restrict__ fa, cons
 // corner), as a bit mask over the velocity index.
 __device__ __forceinline__ unsigned outlet_mask(const Geom& g, int y) {
   unsigned m = 1u << 3;
-  const bool py = g.side[kS] == kPeriodic;
+  const bool py = side_of(g, kS) == kPeriodic;
   if (y - 1 >= 0 || py) m |= 1u << 6;       // e = (-1, 1): source (nx, y-1)
   if (y + 1 < g.ny || py) m |= 1u << 7;     // e = (-1,-1): source (nx, y+1)
   return m;
@@ -494,11 +502,11 @@ __device__ __forceinline__ bool region_coords(const Geom& g, int x, int y, int& 
   gx = x;
   gy = y;
   if (gx < 0 || gx >= g.nx) {
-    if (g.side[kW] == kPeriodic) gx = gx < 0 ? gx + g.nx : gx - g.nx;
+    if (side_of(g, kW) == kPeriodic) gx = gx < 0 ? gx + g.nx : gx - g.nx;
     else ok = false;
   }
   if (gy < 0 || gy >= g.ny) {
-    if (g.side[kS] == kPeriodic) gy = gy < 0 ? gy + g.ny : gy - g.ny;
+    if (side_of(g, kS) == kPeriodic) gy = gy < 0 ? gy + g.ny : gy - g.ny;
     else ok = false;
   }
   gx = gx < 0 ? 0 : (gx >= g.nx ? g.nx - 1 : gx);
@@ -517,7 +525,7 @@ __device__ __forceinline__ bool region_node(const Geom& g, const uint8_t* __rest
 // lies beyond a non-periodic side (e_a points away from that side), and of
 // the populations that leave across a periodic side.
 __device__ __forceinline__ unsigned side_links(const Geom& g, int x, int y) {
-  const bool px = g.side[kW] == kPeriodic, py = g.side[kS] == kPeriodic;
+  const bool px = side_of(g, kW) == kPeriodic, py = side_of(g, kS) == kPeriodic;
   unsigned m = 0;
   if (!px && x == 0) m |= (1u << 1) | (1u << 5) | (1u << 8);
   if (!px && x == g.nx - 1) m |= (1u << 3) | (1u << 6) | (1u << 7);
@@ -526,7 +534,7 @@ __device__ __forceinline__ unsigned side_links(const Geom& g, int x, int y) {
   return m;
 }
 __device__ __forceinline__ unsigned periodic_links(const Geom& g, int x, int y) {
-  const bool px = g.side[kW] == kPeriodic, py = g.side[kS] == kPeriodic;
+  const bool px = side_of(g, kW) == kPeriodic, py = side_of(g, kS) == kPeriodic;
   unsigned m = 0;
   if (px && x == 0) m |= (1u << 3) | (1u << 6) | (1u << 7);
   if (px && x == g.nx - 1) m |= (1u << 1) | (1u << 5) | (1u << 8);
@@ -559,13 +567,13 @@ __device__ __forceinline__ void ghost_writes(typename S::T* __restrict__ fb, con
                                              unsigned wave_leave) {
   using C = typename S::C;
   using T = typename S::T;
-  const bool px = g.side[kW] == kPeriodic, py = g.side[kS] == kPeriodic;
+  const bool px = side_of(g, kW) == kPeriodic, py = side_of(g, kS) == kPeriodic;
   if (wave_bounce) {
     const Rsrc r = lattice_rsrc(fb);
     const uint32_t off = uint32_t(gidx(g, x, y)) * uint32_t(sizeof(T));
     // kind of the side crossed in x and in y by this node's links
-    const int kx = x == 0 ? g.side[kW] : g.side[kE];
-    const int ky = y == 0 ? g.side[kS] : g.side[kN];
+    const int kx = x == 0 ? side_of(g, kW) : side_of(g, kE);
+    const int ky = y == 0 ? side_of(g, kS) : side_of(g, kN);
     const C H = C(g.ny), yy = C(y) + C(0.5);
     const C uin = C(4) * k.u_in_max * yy * (H - yy) * rcp(H * H);
 #pragma unroll
@@ -601,6 +609,138 @@ __device__ __forceinline__ void ghost_writes(typename S::T* __restrict__ fb, con
       }
       if (valid) fb[(long long)a * g.plane + gidx(g, tx - ex, ty - ey)] = S::enc(d[a], k.scale);
     }
+  }
+}
+
+// Boundary slots of the fused step, with every test that selects a link
+// uniform across the wavefront.  A wavefront covers one lattice row y (so
+// "y on the first / last row" is uniform) and 64 consecutive columns from
+// x0 (wcol, ecol: the wavefront holds column 0, column nx - 1); the only per-lane
+// choice left is which lanes store.  The moving-wall terms are uniform too.
+// Each slot is written at the node's own offset plus a uniform shift.
+//
+// Half-way bounce-back across a side (eq. 2b with a wall, lid or inlet at
+// the source, Sec. 6): slot (x - e_a, y - e_a,y) of plane a receives
+// d_opp(a) + 6 w_a rho0 (e_a . u_w).  Links through a corner (source beyond
+// two non-periodic sides) are stationary and written by the W/E handler; the
+// S/N handler takes the links that cross its side only.  An outlet side
+// takes no bounce-back (its links are completed by extrapolation), except
+// at its corners.
+// Periodic sides: the population d_a that leaves across a periodic side goes
+// to the frame slot its wrapped target pulls from; corners that wrap on both
+// axes are written by the x handler.
+template <class S>
+__device__ __forceinline__ void side_slots(typename S::T* __restrict__ fb, const Geom& g,
+                                           const Consts<typename S::C>& k, int x, int y,
+                                           bool wcol, bool ecol, const typename S::C d[9]) {
+  using C = typename S::C;
+  using T = typename S::T;
+  const bool srow = y == 0, nrow = y == g.ny - 1;
+  if (!(wcol || ecol || srow || nrow)) return;
+  const bool px = side_of(g, kW) == kPeriodic, py = side_of(g, kS) == kPeriodic;
+  const Rsrc r = lattice_rsrc(fb);
+  const int node = gidx(g, x, y);
+  // slot (x + sx, y + sy) of plane a: the plane in the scalar offset (as in
+  // every population access), the shift in the vector offset
+  struct Slot {
+    uint32_t vo, so;
+  };
+  auto shift = [&](int a, int sx, int sy) {
+    return Slot{uint32_t(node + sx + sy * g.pitch) * uint32_t(sizeof(T)),
+                uint32_t(a * g.plane) * uint32_t(sizeof(T))};
+  };
+  auto put = [&](bool on, Slot sl, C v) {
+    if (on) Buf<T>::template st<0>(r, sl.vo, sl.so, S::enc(v, k.scale));
+  };
+  // inlet profile at this row (uniform)
+  auto u_inlet = [&]() {
+    const C H = C(g.ny), yy = C(y) + C(0.5);
+    return C(4) * k.u_in_max * yy * (H - yy) * rcp(H * H);
+  };
+  // one of the three links a = A0, A1, A2 of side sd (e_a pointing into the
+  // lattice across it); on: this lane's node lies on that side
+  auto bounce_x = [&](int sd, bool on) {
+    const int kind = side_of(g, sd);
+    const C ux = kind == kInlet ? u_inlet() : C(0);
+    const C uy = kind == kLid ? k.u_lid : C(0);
+    const int A[3] = {sd == kW ? 1 : 3, sd == kW ? 5 : 6, sd == kW ? 8 : 7};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const int a = A[i], ex = ex_of(a), ey = ey_of(a);
+      const bool corner = !py && ((ey > 0 && srow) || (ey < 0 && nrow));
+      if (!corner && kind == kOutlet) continue;
+      const C corr = corner ? C(0) : C(6) * w_of<C>(a) * k.rho0 * (C(ex) * ux + C(ey) * uy);
+      put(on, shift(a, -ex, -ey), d[opp_of(a)] + corr);
+    }
+  };
+  auto bounce_y = [&](int sd) {
+    const int kind = side_of(g, sd);
+    const C ux = kind == kLid ? k.u_lid : C(0);
+    const int A[3] = {sd == kS ? 2 : 4, sd == kS ? 5 : 8, sd == kS ? 6 : 7};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const int a = A[i], ex = ex_of(a), ey = ey_of(a);
+      // lanes whose source also lies beyond a non-periodic W/E side: corner
+      const bool on = px || !((ex > 0 && x == 0) || (ex < 0 && x == g.nx - 1));
+      const C corr = C(6) * w_of<C>(a) * k.rho0 * C(ex) * ux;
+      put(on, shift(a, -ex, -ey), d[opp_of(a)] + corr);
+    }
+  };
+  if (!px) {
+    if (wcol) bounce_x(kW, x == 0);
+    if (ecol) bounce_x(kE, x == g.nx - 1);
+  } else {
+    // x-periodic: d_a leaving across W (e_x < 0) or E (e_x > 0)
+#pragma unroll
+    for (int a = 1; a < 9; ++a) {
+      const int ex = ex_of(a), ey = ey_of(a);
+      if (ex == 0) continue;
+      if (ex < 0 ? !wcol : !ecol) continue;
+      const bool on = ex < 0 ? x == 0 : x == g.nx - 1;
+      const bool cy = (ey > 0 && nrow) || (ey < 0 && srow);
+      if (cy && !py) continue;   // target beyond a wall: bounce-back takes it
+      put(on, shift(a, -ex * g.nx, cy ? -ey * g.ny : 0), d[a]);
+    }
+  }
+  if (!py) {
+    if (srow) bounce_y(kS);
+    if (nrow) bounce_y(kN);
+  } else {
+    // y-periodic: d_a leaving across S (e_y < 0) or N (e_y > 0); lanes whose
+    // target also crosses a W/E side are left to the x handler or to the
+    // bounce-back of that side
+#pragma unroll
+    for (int a = 1; a < 9; ++a) {
+      const int ex = ex_of(a), ey = ey_of(a);
+      if (ey == 0) continue;
+      if (ey < 0 ? !srow : !nrow) continue;
+      const bool on = !((ex > 0 && x == g.nx - 1) || (ex < 0 && x == 0));
+      put(on, shift(a, 0, -ey * g.ny), d[a]);
+    }
+  }
+}
+
+// Half-way bounce-back from solid nodes inside the lattice (stationary):
+// link a of this node whose source is solid (bit a of solid_src; sources
+// beyond a non-periodic side excluded) gets slot (x - e_a, y - e_a,y) of
+// plane a (unwrapped: across a periodic side that is the frame slot the
+// node pulls from) = d_opp(a).
+template <class S>
+__device__ __forceinline__ void solid_slots(typename S::T* __restrict__ fb, const Geom& g,
+                                            const Consts<typename S::C>& k, int x, int y,
+                                            const typename S::C d[9], unsigned solid_src) {
+  using T = typename S::T;
+  if (__builtin_amdgcn_ballot_w64(solid_src != 0) == 0) return;
+  const Rsrc r = lattice_rsrc(fb);
+  const int node = gidx(g, x, y);
+#pragma unroll
+  for (int a = 1; a < 9; ++a) {
+    const bool on = (solid_src >> a) & 1u;
+    if (__builtin_amdgcn_ballot_w64(on) == 0) continue;
+    const uint32_t vo = uint32_t(node - ex_of(a) - ey_of(a) * g.pitch) * uint32_t(sizeof(T));
+    if (on)
+      Buf<T>::template st<0>(r, vo, uint32_t(a * g.plane) * uint32_t(sizeof(T)),
+                             S::enc(d[opp_of(a)], k.scale));
   }
 }
 

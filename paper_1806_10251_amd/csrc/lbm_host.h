@@ -88,7 +88,8 @@ inline Geom make_geom_for(int nx, int ny, const int32_t side[4], size_t esize) {
   Geom g{};
   g.nx = nx;
   g.ny = ny;
-  for (int s = 0; s < 4; ++s) g.side[s] = side[s];
+  g.sides = 0;
+  for (int s = 0; s < 4; ++s) g.sides |= (side[s] & 15) << (4 * s);
   const int line = int(128 / esize);  // elements per 128-byte line
   g.padx = line;
   g.pitch = ((nx + 2 * line) + line - 1) / line * line;

@@ -170,13 +170,13 @@ __device__ __forceinline__ void block_partials(double acc[4], double (*s_red)[4]
 // region extends one node beyond the lattice; coordinates further out occur
 // only in ragged tiles, whose extra nodes feed no output).
 __device__ __forceinline__ int col_of(const Geom& g, int x) {
-  const bool px = g.side[kW] == kPeriodic;
+  const bool px = side_of(g, kW) == kPeriodic;
   if (x < 0) return px ? x + g.nx : 0;
   if (x >= g.nx) return px ? (x - g.nx < g.nx ? x - g.nx : g.nx - 1) : g.nx - 1;
   return x;
 }
 __device__ __forceinline__ int row_of(const Geom& g, int y) {
-  const bool py = g.side[kS] == kPeriodic;
+  const bool py = side_of(g, kS) == kPeriodic;
   if (y < 0) return py ? y + g.ny : 0;
   if (y >= g.ny) return py ? (y - g.ny < g.ny ? y - g.ny : g.ny - 1) : g.ny - 1;
   return y;
@@ -225,7 +225,9 @@ __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
   const C SENT = C(HUGE_VALF);   // LDS value of a solid region node
   const Geom& g = args.g;
   const int lane = threadIdx.x;
-  const int w = threadIdx.y;
+  // blocks are 64 x BY threads: each wavefront is one threadIdx.y, so the
+  // row index is wave-uniform (scalar row arithmetic and branches)
+  const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.y));
   const int tx = tile % args.tiles_x;
   const int ty = tile / args.tiles_x;
   const int x = tx * kLanes + lane;
@@ -387,6 +389,7 @@ __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
     }
   }
   __syncthreads();
+  const Consts<C>& kc = k;
 
   // ---- phase 2: gradient, collision, stores, boundary slots
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -405,7 +408,7 @@ __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
     if (OBST && !INT && own == SENT) continue;  // solid node
     auto sub = [&](C v) { return (OBST && !INT && v == SENT) ? own : v; };
     C drx, dry;
-    if (k.stencil == 0) {
+    if (uflag(k.stencil) == 0) {
       // isotropic: d rho = 3 sum_a w_a e_a rho(x + e_a)
       const C ne = sub(nNE), nw = sub(nNW), se = sub(nSE), sw = sub(nSW);
       drx = (sub(nE) - sub(nW)) * (C(1) / C(3)) + ((ne - nw) + (se - sw)) * (C(1) / C(12));
@@ -419,7 +422,7 @@ __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
       // d_x u_x and d_y u_y with the density-gradient stencil and neighbour rule
       auto su = [&](int rr, int cc) { return s_rho[rr][cc] == SENT ? s_u[ry][c] : s_u[rr][cc]; };
       auto sv = [&](int rr, int cc) { return s_rho[rr][cc] == SENT ? s_v[ry][c] : s_v[rr][cc]; };
-      if (k.stencil == 0) {
+      if (uflag(k.stencil) == 0) {
         sxx = (su(ry, c + 1) - su(ry, c - 1)) * (C(1) / C(3)) +
               ((su(ry + 1, c + 1) - su(ry + 1, c - 1)) + (su(ry - 1, c + 1) - su(ry - 1, c - 1))) *
                   (C(1) / C(12));
@@ -431,32 +434,29 @@ __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
         syy = C(0.5) * (sv(ry + 1, c) - sv(ry - 1, c));
       }
     }
-    C fx = k.fx, fy = k.fy;
+    C fx = kc.fx, fy = kc.fy;
     if (has_force) {
       fx = force[y * g.nx + x];
       fy = force[g.nx * g.ny + y * g.nx + x];
     }
     C drho, ux, uy;
-    const int gd = collide<C, VAR>(d[r], drx, dry, k, fx, fy, drho, ux, uy, sxx, syy);
-    finish_node<S, FL, (VAR & kVarNts) != 0>(fb, args, k, d[r], gidx(g, x, y), y * g.nx + x, drho, ux, uy,
+    const int gd = collide<C, VAR>(d[r], drx, dry, kc, fx, fy, drho, ux, uy, sxx, syy);
+    finish_node<S, FL, (VAR & kVarNts) != 0>(fb, args, kc, d[r], gidx(g, x, y), y * g.nx + x, drho, ux, uy,
                        gd, acc);
-    // boundary links: the source of link a (the neighbour at -e_a) lies
-    // beyond a non-periodic side or is a solid node; populations leaving
-    // across a periodic side
-    // a wavefront touches a side only in the first / last tile column or on
-    // the first / last lattice row (uniform test)
-    const bool side_wave = x0 == 0 || x0 + kLanes >= g.nx || y == 0 || y == g.ny - 1;
-    if (!INT && (side_wave || OBST)) {
-      unsigned bounce = side_links(g, x, y);
+    // boundary slots: links whose source lies beyond a side or is a solid
+    // node, populations leaving across a periodic side
+    if (!INT) {
+      side_slots<S>(fb, g, kc, x, y, x0 == 0, x0 + kLanes >= g.nx, d[r]);
       if (OBST) {
-        bounce |= (nW == SENT ? 1u << 1 : 0u) | (nS == SENT ? 1u << 2 : 0u) |
-                  (nE == SENT ? 1u << 3 : 0u) | (nN == SENT ? 1u << 4 : 0u) |
-                  (nSW == SENT ? 1u << 5 : 0u) | (nSE == SENT ? 1u << 6 : 0u) |
-                  (nNE == SENT ? 1u << 7 : 0u) | (nNW == SENT ? 1u << 8 : 0u);
+        unsigned src = (nW == SENT ? 1u << 1 : 0u) | (nS == SENT ? 1u << 2 : 0u) |
+                       (nE == SENT ? 1u << 3 : 0u) | (nN == SENT ? 1u << 4 : 0u) |
+                       (nSW == SENT ? 1u << 5 : 0u) | (nSE == SENT ? 1u << 6 : 0u) |
+                       (nNE == SENT ? 1u << 7 : 0u) | (nNW == SENT ? 1u << 8 : 0u);
+        // a mirrored halo node that is solid is not a source: the link
+        // crosses the side
+        src &= ~side_links(g, x, y);
+        solid_slots<S>(fb, g, kc, x, y, d[r], src);
       }
-      const unsigned leave = periodic_links(g, x, y);
-      const unsigned wb = wave_or(bounce), wl = wave_or(leave);
-      if (wb | wl) ghost_writes<S>(fb, g, k, x, y, d[r], bounce, leave, wb, wl);
     }
     if (OUTL && x == g.nx - 1) {
       C* ho = static_cast<C*>(args.hist_out);

@@ -67,7 +67,7 @@ void launch_step<LBM_STEP_STORAGE, LBM_STEP_FLAVOR>(int by, int rows, int var, c
                                                     const void* consts, hipStream_t st) {
   const Consts<C>& k = *static_cast<const Consts<C>*>(consts);
   const bool obst = a.solid != nullptr;
-  const bool outl = a.g.side[kE] == kOutlet;
+  const bool outl = side_of(a.g, kE) == kOutlet;
   switch (by * 100 + rows) {
     case 1601: go<16, 1>(obst, outl, var, src, dst, a, k, st); break;
     case 801: go<8, 1>(obst, outl, var, src, dst, a, k, st); break;
