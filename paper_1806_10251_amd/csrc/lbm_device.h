@@ -197,6 +197,17 @@ struct Geom {
 __host__ __device__ __forceinline__ int side_of(const Geom& g, int s) {
   return (g.sides >> (4 * s)) & 15;
 }
+// Periodic in x / y.  CL: the lattice is known at compile time to be closed
+// (every side a wall or a lid), which removes the periodic, inlet and outlet
+// code from a kernel.
+template <bool CL = false>
+__device__ __forceinline__ bool periodic_x(const Geom& g) {
+  return !CL && side_of(g, kW) == kPeriodic;
+}
+template <bool CL = false>
+__device__ __forceinline__ bool periodic_y(const Geom& g) {
+  return !CL && side_of(g, kS) == kPeriodic;
+}
 
 // Element offsets within a plane and across the nine planes fit in 32 bits
 // (enforced at creation), so loads and stores use a 64-bit base plus a
@@ -524,8 +535,9 @@ __device__ __forceinline__ bool region_node(const Geom& g, const uint8_t* __rest
 // Bit masks over the velocity index of the links of node (x, y) whose source
 // lies beyond a non-periodic side (e_a points away from that side), and of
 // the populations that leave across a periodic side.
+template <bool CL = false>
 __device__ __forceinline__ unsigned side_links(const Geom& g, int x, int y) {
-  const bool px = side_of(g, kW) == kPeriodic, py = side_of(g, kS) == kPeriodic;
+  const bool px = periodic_x<CL>(g), py = periodic_y<CL>(g);
   unsigned m = 0;
   if (!px && x == 0) m |= (1u << 1) | (1u << 5) | (1u << 8);
   if (!px && x == g.nx - 1) m |= (1u << 3) | (1u << 6) | (1u << 7);
@@ -629,7 +641,7 @@ __device__ __forceinline__ void ghost_writes(typename S::T* __restrict__ fb, con
 // Periodic sides: the population d_a that leaves across a periodic side goes
 // to the frame slot its wrapped target pulls from; corners that wrap on both
 // axes are written by the x handler.
-template <class S>
+template <class S, bool CL = false>
 __device__ __forceinline__ void side_slots(typename S::T* __restrict__ fb, const Geom& g,
                                            const Consts<typename S::C>& k, int x, int y,
                                            bool wcol, bool ecol, const typename S::C d[9]) {
@@ -637,7 +649,7 @@ __device__ __forceinline__ void side_slots(typename S::T* __restrict__ fb, const
   using T = typename S::T;
   const bool srow = y == 0, nrow = y == g.ny - 1;
   if (!(wcol || ecol || srow || nrow)) return;
-  const bool px = side_of(g, kW) == kPeriodic, py = side_of(g, kS) == kPeriodic;
+  const bool px = periodic_x<CL>(g), py = periodic_y<CL>(g);
   const Rsrc r = lattice_rsrc(fb);
   const int node = gidx(g, x, y);
   // slot (x + sx, y + sy) of plane a: the plane in the scalar offset (as in
@@ -661,14 +673,14 @@ __device__ __forceinline__ void side_slots(typename S::T* __restrict__ fb, const
   // lattice across it); on: this lane's node lies on that side
   auto bounce_x = [&](int sd, bool on) {
     const int kind = side_of(g, sd);
-    const C ux = kind == kInlet ? u_inlet() : C(0);
+    const C ux = !CL && kind == kInlet ? u_inlet() : C(0);
     const C uy = kind == kLid ? k.u_lid : C(0);
     const int A[3] = {sd == kW ? 1 : 3, sd == kW ? 5 : 6, sd == kW ? 8 : 7};
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       const int a = A[i], ex = ex_of(a), ey = ey_of(a);
       const bool corner = !py && ((ey > 0 && srow) || (ey < 0 && nrow));
-      if (!corner && kind == kOutlet) continue;
+      if (!CL && !corner && kind == kOutlet) continue;
       const C corr = corner ? C(0) : C(6) * w_of<C>(a) * k.rho0 * (C(ex) * ux + C(ey) * uy);
       put(on, shift(a, -ex, -ey), d[opp_of(a)] + corr);
     }

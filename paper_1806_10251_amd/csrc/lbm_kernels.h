@@ -169,14 +169,16 @@ __device__ __forceinline__ void block_partials(double acc[4], double (*s_red)[4]
 // side, else mirrored onto the edge node across the half-way wall (the
 // region extends one node beyond the lattice; coordinates further out occur
 // only in ragged tiles, whose extra nodes feed no output).
+template <bool CL>
 __device__ __forceinline__ int col_of(const Geom& g, int x) {
-  const bool px = side_of(g, kW) == kPeriodic;
+  const bool px = periodic_x<CL>(g);
   if (x < 0) return px ? x + g.nx : 0;
   if (x >= g.nx) return px ? (x - g.nx < g.nx ? x - g.nx : g.nx - 1) : g.nx - 1;
   return x;
 }
+template <bool CL>
 __device__ __forceinline__ int row_of(const Geom& g, int y) {
-  const bool py = side_of(g, kS) == kPeriodic;
+  const bool py = periodic_y<CL>(g);
   if (y < 0) return py ? y + g.ny : 0;
   if (y >= g.ny) return py ? (y - g.ny < g.ny ? y - g.ny : g.ny - 1) : g.ny - 1;
   return y;
@@ -209,7 +211,8 @@ __device__ __forceinline__ void store_velocity(const C dd[9], bool on, int gx, i
 // image across the half-way wall (the clamped lattice node, the density-
 // gradient reading at the lattice sides), so only solid nodes carry the
 // sentinel (their density is replaced by the differentiating node's own).
-template <class S, int BY, int R, int FL, bool OBST, bool OUTL, int VAR = 0, bool INT = false>
+template <class S, int BY, int R, int FL, bool OBST, bool OUTL, int VAR = 0, bool INT = false,
+          bool CL = false>
 __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
                                           typename S::T* __restrict__ fb, const StepArgs& args,
                                           const Consts<typename S::C>& k, int tile,
@@ -245,14 +248,14 @@ __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
   static_assert(BY >= 2, "the first and the last wavefront each pull one halo row");
   // lattice coordinates of the region nodes: the lane's column (per lane),
   // every row (uniform), the two halo columns (uniform)
-  const int gx = INT ? x : col_of(g, x);
+  const int gx = INT ? x : col_of<CL>(g, x);
   C d[R][9];
   C us[R], vs[R];
   bool sol[R];
   int gyr[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    gyr[r] = INT ? y0 + r : row_of(g, y0 + r);
+    gyr[r] = INT ? y0 + r : row_of<CL>(g, y0 + r);
     pull9<S>(fa, g, k, gx, gyr[r], d[r]);
     sol[r] = OBST && args.solid[gyr[r] * g.nx + gx];
   }
@@ -260,7 +263,7 @@ __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
   const bool row_wave = w == 0 || w == BY - 1;
   const int hy = w == 0 ? ytile - 1 : ytile + RO;
   const int hlr = w == 0 ? 0 : RR - 1;
-  const int hgy = INT ? hy : row_of(g, hy);
+  const int hgy = INT ? hy : row_of<CL>(g, hy);
   C dm[9];
   bool hrsol = false;
   if (row_wave) {
@@ -280,8 +283,8 @@ __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
     lr = hlr;
     return hgy;
   };
-  const int hxl = INT ? x0 - 1 : col_of(g, x0 - 1);
-  const int hxr = INT ? x0 + kLanes : col_of(g, x0 + kLanes);
+  const int hxl = INT ? x0 - 1 : col_of<CL>(g, x0 - 1);
+  const int hxr = INT ? x0 + kLanes : col_of<CL>(g, x0 + kLanes);
   // A right halo column on (or mirrored onto) the OUTLET column needs the
   // outlet links of its nodes; lane 63 then pulls it node by node (the left
   // column stays cooperative), as the finite-difference variant does for both
@@ -446,7 +449,7 @@ __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
     // boundary slots: links whose source lies beyond a side or is a solid
     // node, populations leaving across a periodic side
     if (!INT) {
-      side_slots<S>(fb, g, kc, x, y, x0 == 0, x0 + kLanes >= g.nx, d[r]);
+      side_slots<S, CL>(fb, g, kc, x, y, x0 == 0, x0 + kLanes >= g.nx, d[r]);
       if (OBST) {
         unsigned src = (nW == SENT ? 1u << 1 : 0u) | (nS == SENT ? 1u << 2 : 0u) |
                        (nE == SENT ? 1u << 3 : 0u) | (nN == SENT ? 1u << 4 : 0u) |
@@ -454,7 +457,7 @@ __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
                        (nNE == SENT ? 1u << 7 : 0u) | (nNW == SENT ? 1u << 8 : 0u);
         // a mirrored halo node that is solid is not a source: the link
         // crosses the side
-        src &= ~side_links(g, x, y);
+        src &= ~side_links<CL>(g, x, y);
         solid_slots<S>(fb, g, kc, x, y, d[r], src);
       }
     }
@@ -467,7 +470,7 @@ __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
   if (FL == kCheck) block_partials<BY>(acc, s_red, lane, w, args.partials + (long long)tile * 4);
 }
 
-template <class S, int BY, int R, int FL, bool OBST, bool OUTL, int VAR = 0>
+template <class S, int BY, int R, int FL, bool OBST, bool OUTL, int VAR = 0, bool CL = false>
 __global__ __launch_bounds__(kLanes* BY) void step_kernel(const typename S::T* __restrict__ fa,
                                                           typename S::T* __restrict__ fb,
                                                           const StepArgs args,
@@ -486,12 +489,12 @@ __global__ __launch_bounds__(kLanes* BY) void step_kernel(const typename S::T* _
     const int x0 = (tile % args.tiles_x) * kLanes, y0 = (tile / args.tiles_x) * (BY * R);
     if (x0 >= 2 && x0 + kLanes + 1 <= args.g.nx - 2 && y0 >= 2 &&
         y0 + BY * R + 1 <= args.g.ny - 2) {
-      step_tile<S, BY, R, FL, OBST, OUTL, VAR, true>(fa, fb, args, k, tile, s_rho, s_red,
+      step_tile<S, BY, R, FL, OBST, OUTL, VAR, true, CL>(fa, fb, args, k, tile, s_rho, s_red,
                                                      s_uv[0], s_uv[FDS ? 1 : 0]);
       return;
     }
   }
-  step_tile<S, BY, R, FL, OBST, OUTL, VAR>(fa, fb, args, k, tile, s_rho, s_red, s_uv[0],
+  step_tile<S, BY, R, FL, OBST, OUTL, VAR, false, CL>(fa, fb, args, k, tile, s_rho, s_red, s_uv[0],
                                            s_uv[FDS ? 1 : 0]);
 }
 
