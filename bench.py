@@ -98,6 +98,19 @@ def measured_traffic(storage, n, by, rows):
         return None
 
 
+def timed_window(warmup, steps, K):
+    """What the timed steps were: the library runs the check step (velocity
+    residual and mass, FP64 partials and their reduction) at every step whose
+    1-based index is a multiple of K, and stores the velocity one step
+    before; the other steps are plain."""
+    def multiples(lo, hi):          # multiples of K in [lo, hi]
+        return hi // K - (lo - 1) // K
+    check = multiples(warmup + 1, warmup + steps)
+    store = multiples(warmup + 2, warmup + steps + 1)
+    return {"steps": steps, "plain": steps - check - store, "store": store, "check": check,
+            "check_every": K, "graph_windows": "captured graphs of K steps, replayed"}
+
+
 def _case_kw(k):
     kw = {"u_lid": k.u_ref} if k.kind == "cavity" else {"u_in_max": k.u_ref}
     return dict(nu=k.nu, gamma=k.gamma, **kw)
@@ -411,7 +424,11 @@ def main():
                      "traffic": measured_traffic(args.storage, n, by, rows),
                      "note": f"{bpl} B/LUP algorithmic (each population read and written once) x "
                              f"{n * n} nodes per launch / average step time "
-                             f"{step_ms_dev * 1e3:.2f} us from HIP events"},
+                             f"{step_ms_dev * 1e3:.2f} us from HIP events on the library's "
+                             f"stream over the timed window (its plain, store and check steps "
+                             f"and check reductions); traffic: HBM bytes per plain-step launch "
+                             f"from the committed counter summary"},
+        "timed_window": timed_window(args.warmup, args.steps, K),
         "residual_at_end": resid,
         "mass_drift": None if mass is None else mass - n * n,
     }
