@@ -111,50 +111,22 @@ def timed_window(warmup, steps, K):
             "check_every": K, "graph_windows": "captured graphs of K steps, replayed"}
 
 
-def _case_kw(k):
-    kw = {"u_lid": k.u_ref} if k.kind == "cavity" else {"u_in_max": k.u_ref}
-    return dict(nu=k.nu, gamma=k.gamma, **kw)
-
-
 WEIGHTS = os.path.join(ROOT, "paper_1806_10251_amd", "weights", "unet_cavity128.npy")
 
 
+def _case_kw(k):
+    from paper_1806_10251_amd import steady
+    return steady.case_kw(k)
+
+
 def _batch_arm(lbm, cases, choice, tol, max_steps, warm_net=None, filter_at=()):
-    """One batched run of every case to tol: optional warm start (the
-    network's prediction, computed inside the timed region) and filter
-    steps.  Returns (steps, status, seconds, [(ux, uy)] per case)."""
-    import numpy as np
-    import torch
-
-    from paper_1806_10251_amd import autotune, steady, surrogate
-
-    grids = [lbm.make_grid(k.nx, k.ny, k.sides) for k in cases]
-    params = [lbm.make_params(storage="f64", check_every=100, **_case_kw(k)) for k in cases]
-    b = lbm.Batch(grids, [k.mask for k in cases], params)
-    autotune.apply_batch_choice(b, choice)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    if warm_net is not None:
-        surrogate.warm_init(warm_net, cases)(0, len(cases), b)
-    done = 0
-    for at in filter_at:
-        b.run(0.0, at - done)
-        done = at
-        b.average_last_two()
-    steps, st, _ = steady.run_batch(b, tol=tol, max_steps=max_steps - done)
-    torch.cuda.synchronize()
-    sec = time.perf_counter() - t0
-    fields = [b.fields(i, k.ny, k.nx)[1:] for i, k in enumerate(cases)]
-    b.close()
-    return np.where(st == 3, steps, steps + done), st, sec, fields
+    from paper_1806_10251_amd import steady
+    return steady.batch_arm(cases, tol, max_steps, "f64", choice, warm_net, filter_at)
 
 
 def _accuracy(cases, fields, ref, ok):
-    """max |u - u_ref| / U over the cases in ok."""
-    import numpy as np
-    errs = [max(np.abs(fields[i][0] - ref[i][0]).max(), np.abs(fields[i][1] - ref[i][1]).max()) /
-            cases[i].u_ref for i in ok]
-    return float(max(errs)) if errs else None
+    from paper_1806_10251_amd import steady
+    return steady.max_error(cases, fields, ref, ok)
 
 
 def time_to_steady(lbm, n_cases, side_hi, max_steps, seed=1806, tol=1e-8):

@@ -78,6 +78,121 @@ def run_batch(batch: L.Batch, tol=1e-8, max_steps=2_000_000, plateau_checks=0, f
 
 
 # ---------------------------------------------------------------------------
+# Time to steady state of a case mix: the plain method (one case after
+# another), the batch, and the batch with the two-step filter and the
+# learned warm start.
+# ---------------------------------------------------------------------------
+
+def case_kw(k):
+    """Lattice parameters of a drawn case (workloads.draw_cases)."""
+    kw = {"u_lid": k.u_ref} if k.kind == "cavity" else {"u_in_max": k.u_ref}
+    return dict(nu=k.nu, gamma=k.gamma, **kw)
+
+
+def batch_arm(cases, tol, max_steps, storage="f64", choice=None, warm_net=None, filter_at=(),
+              plateau=(0, 0.9), segment=None, log=None):
+    """One batched run of every case to tol from rest (or from the
+    network's prediction, computed inside the timed region), with optional
+    filter steps.  segment: run in windows of that many steps (a multiple of
+    the check cadence), retiring finished cases between windows and logging
+    each window.  Returns (steps, status, seconds, [(ux, uy)] per case)."""
+    import torch
+
+    from . import autotune, surrogate
+    grids = [L.make_grid(k.nx, k.ny, k.sides) for k in cases]
+    params = [L.make_params(storage=storage, check_every=100, **case_kw(k)) for k in cases]
+    b = L.Batch(grids, [k.mask for k in cases], params)
+    if choice is not None:
+        autotune.apply_batch_choice(b, choice)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    if warm_net is not None:
+        surrogate.warm_init(warm_net, cases)(0, len(cases), b)
+    done = 0
+    for at in filter_at:
+        b.run(0.0, at - done)
+        done = at
+        b.average_last_two()
+    if segment is None:
+        steps, st, _ = run_batch(b, tol=tol, max_steps=max_steps - done,
+                                 plateau_checks=plateau[0], factor=plateau[1])
+        total = np.where(st == 3, steps, steps + done)
+    else:
+        n = len(cases)
+        total = np.full(n, -1, np.int64)
+        st = np.zeros(n, np.int32)
+        active = np.ones(n, bool)
+        while done < max_steps and active.any():
+            b.set_enabled(active.astype(np.int32))
+            b.set_plateau(*plateau)
+            m = min(segment, max_steps - done)
+            steps = b.run(tol, m)
+            now = b.status()
+            for i in range(n):
+                if active[i] and now[i] in (1, 2, 3):
+                    total[i] = done + abs(int(steps[i]))
+                    st[i] = now[i]
+                    active[i] = False
+            done += m
+            if log:
+                log(f"[tts] window to {done} steps: {int((~active).sum())}/{n} cases "
+                    f"retired, {time.perf_counter() - t0:.1f} s")
+        total[active] = done
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    fields = [b.fields(i, k.ny, k.nx)[1:] for i, k in enumerate(cases)]
+    b.close()
+    return total, st, sec, fields
+
+
+_STATUS = {1: "converged", 3: "diverged", 0: "max_steps", 2: "plateau"}
+
+
+def plain_arm(cases, tol, max_steps, storage="f64", log=None):
+    """Every case on its own lattice, one after another, from rest.
+    Returns (steps, status codes as in run_batch, seconds, fields)."""
+    import torch
+    code = {v: k for k, v in _STATUS.items()}
+    steps, status, fields, sec = [], [], [], 0.0
+    for i, k in enumerate(cases):
+        if log and i % 16 == 0:
+            log(f"[tts] plain: case {i}/{len(cases)}, {sec:.1f} s")
+        lat = L.Lattice(k.nx, k.ny, k.sides, solid=k.mask, storage=storage, check_every=100,
+                        **case_kw(k))
+        torch.cuda.synchronize()
+        r = run_single(lat, tol=tol, max_steps=max_steps)
+        fields.append(lat.fields()[1:])
+        lat.close()
+        sec += r.seconds
+        steps.append(r.steps)
+        status.append(code[r.status])
+    return np.array(steps), np.array(status, np.int32), sec, fields
+
+
+def max_error(cases, fields, ref, which):
+    """max |u - u_ref| / U over the cases in which (None if empty)."""
+    errs = [max(np.abs(fields[i][0] - ref[i][0]).max(), np.abs(fields[i][1] - ref[i][1]).max()) /
+            cases[i].u_ref for i in which]
+    return float(max(errs)) if errs else None
+
+
+def arm_summary(name, cases, steps, status, sec, fields, ref=None, ref_ok=None, base_s=None):
+    """JSON-ready summary of one arm: seconds, total steps, outcome counts,
+    and the error against the reference fields over the cases converged in
+    both."""
+    out = {"arm": name, "seconds": round(sec, 3), "steps": int(np.sum(steps)),
+           "status": {_STATUS[c]: int((status == c).sum()) for c in sorted(set(status.tolist()))}}
+    if ref is not None:
+        ok = [i for i in range(len(cases)) if status[i] == 1 and ref_ok[i]]
+        out["max_err"] = max_error(cases, fields, ref, ok)
+        out["compared_cases"] = len(ok)
+    if base_s:
+        out["speedup_vs_plain"] = round(base_s / sec, 3)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Convergence acceleration by preconditioning# ---------------------------------------------------------------------------
 # Convergence acceleration by preconditioning (Sec. 6: the lid-driven cavity
 # at Re = 3200 and the square cylinder at Re = 30 reach their steady states
 # faster as gamma falls).
@@ -125,11 +240,78 @@ def gamma_sweep(kind, size, re, u, gammas, tols=(1e-6, 1e-8), storage="f64",
     return out
 
 
+def mix_time_to_steady(n_cases=256, side_lo=64, side_hi=512, seed=1806, tol=1e-8,
+                       max_steps=100_000, storage="f64", arms=("plain", "batch"), weights=None,
+                       segment=10_000, log=print):
+    """Time to steady state of the seeded batched mix (workloads.draw_cases):
+    each arm in `arms` runs every case to tol (at most max_steps steps) from
+    rest or from the learned warm start.  Arms: "plain" (one lattice after
+    another), "batch", "batch+filter" (two-step filter of the warm start on a
+    cold start), "batch+surrogate" (warm start and filter).  Errors are
+    max |u - u_ref| / U against the first arm's fields, over the cases
+    converged in both.  Batch arms run in windows of `segment` steps.
+    Returns a JSON-ready dict."""
+
+    from . import autotune, surrogate
+    from . import unet as U
+    from workloads import draw_cases
+    cases = draw_cases(n_cases, seed, side_lo=side_lo, side_hi=side_hi)
+    nodes = int(sum(k.nx * k.ny for k in cases))
+    log(f"[tts] {n_cases} cases, {nodes} nodes, storage {storage}, tol {tol:g}, "
+        f"at most {max_steps} steps")
+    grids = [L.make_grid(k.nx, k.ny, k.sides) for k in cases]
+    masks = [k.mask for k in cases]
+    params = [L.make_params(storage=storage, check_every=100, **case_kw(k)) for k in cases]
+    choice, _ = autotune.tune_batch(grids, masks, params, steps=200)
+    net = None
+    if any(a == "batch+surrogate" for a in arms):
+        net = U.UNet(max_batch=16, res=surrogate.RES, seed=0)
+        surrogate.load_into(net, weights or surrogate.DEFAULT_WEIGHTS)
+    results, ref, ref_ok, base_s = [], None, None, None
+    for a in arms:
+        seg = dict(segment=segment, log=log)
+        if a == "plain":
+            r = plain_arm(cases, tol, max_steps, storage, log=log)
+        elif a == "batch":
+            r = batch_arm(cases, tol, max_steps, storage, choice, **seg)
+        elif a == "batch+filter":
+            r = batch_arm(cases, tol, max_steps, storage, choice, filter_at=surrogate.WARM_FILTER,
+                          **seg)
+        elif a == "batch+surrogate":
+            r = batch_arm(cases, tol, max_steps, storage, choice, warm_net=net,
+                          filter_at=surrogate.WARM_FILTER, **seg)
+        else:
+            raise ValueError(f"unknown arm {a!r}")
+        steps, st, sec, fields = r
+        if ref is None:
+            ref, ref_ok = fields, st == 1
+        if a == "plain":
+            base_s = sec
+        results.append(arm_summary(a, cases, steps, st, sec, fields, ref, ref_ok, base_s))
+        log(f"[tts] {results[-1]}")
+    if net is not None:
+        net.close()
+    return {"cases": n_cases, "nodes": nodes, "seed": seed, "tol": tol, "storage": storage,
+            "max_steps": max_steps,
+            "sample": f"seeded mix (seed {seed}) of cavities s x s and channels 4s x s, s in "
+                      f"[{side_lo}, {side_hi}], 1-4 rectangular obstacles covering 5-20%, Re in "
+                      "[50, 1000], gamma log-uniform in [0.05, 1]",
+            "batch_launch": {"block_height": choice[0], "schedule": choice[1]},
+            "error_reference": f"fields of the {arms[0]} arm", "arms": results}
+
+
 def main(argv=None):
     import argparse
     import json
-    ap = argparse.ArgumentParser(description="steps to steady state against gamma")
-    ap.add_argument("cmd", choices=["sweep"])
+    ap = argparse.ArgumentParser(description="steps to steady state against gamma; time to "
+                                             "steady state of the batched mix")
+    ap.add_argument("cmd", choices=["sweep", "tts"])
+    ap.add_argument("--cases", type=int, default=256, help="tts: number of cases")
+    ap.add_argument("--side-lo", type=int, default=64)
+    ap.add_argument("--side-hi", type=int, default=512)
+    ap.add_argument("--seed", type=int, default=1806)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--arms", default="plain,batch,batch+filter,batch+surrogate")
     ap.add_argument("--kind", choices=["cavity", "cylinder"], default="cavity")
     ap.add_argument("--size", type=int, default=400, help="cavity side or cylinder D")
     ap.add_argument("--re", type=float, default=3200.0)
@@ -138,13 +320,27 @@ def main(argv=None):
     ap.add_argument("--gammas", default="1,0.5,0.2,0.1,0.05")
     ap.add_argument("--tols", default="1e-6,1e-8")
     ap.add_argument("--storage", default="f64")
-    ap.add_argument("--max-steps", type=int, default=4_000_000)
+    ap.add_argument("--max-steps", type=int, default=None,
+                    help="sweep: 4000000 by default; tts: 100000 by default")
     a = ap.parse_args(argv)
+    if a.cmd == "tts":
+        import sys
+        import torch
+        if not torch.cuda.is_available():
+            sys.exit("needs a GPU")
+        L.load()
+        out = mix_time_to_steady(a.cases, a.side_lo, a.side_hi, a.seed, a.tol,
+                                 a.max_steps or 100_000,
+                                 a.storage, tuple(a.arms.split(",")),
+                                 log=lambda m: print(m, file=sys.stderr, flush=True))
+        print(json.dumps(out), flush=True)
+        return
     u = a.mach / np.sqrt(3.0)
     gammas = [float(x) for x in a.gammas.split(",")]
     tols = [float(x) for x in a.tols.split(",")]
     for g in gammas:
-        row = gamma_sweep(a.kind, a.size, a.re, u, [g], tols, a.storage, a.max_steps)[0]
+        row = gamma_sweep(a.kind, a.size, a.re, u, [g], tols, a.storage,
+                          a.max_steps or 4_000_000)[0]
         print(json.dumps(row), flush=True)
 
 

@@ -39,6 +39,8 @@ from . import steady
 from . import unet as U
 
 RES = 128
+DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights",
+                               "unet_cavity128.npy")
 
 
 def cavity_cases(n, seed, side, re_lo=50.0, re_hi=500.0):

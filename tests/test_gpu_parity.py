@@ -398,6 +398,31 @@ def test_c4_channel_storage_precision_full_size(lbm):
     assert np.isfinite(errs["bf16"]) and np.isfinite(errs["f16"])
 
 
+def test_c4_shaped_channel_fp32_and_fp64_against_oracle(lbm):
+    """The C4 configuration scaled down 8x: channel 512 x 128, centred square
+    obstacle of side 16 (blockage 1/8), parabolic inlet U_max 0.05, Re 40
+    on the obstacle side, gamma 0.2, convective outlet; 1500 steps.  FP32
+    deviation storage within 1e-5 U of the FP64 oracle, FP64 storage within
+    rounding-order differences."""
+    from workloads import centred_square_mask
+    nx, ny, D, U = 512, 128, 16, 0.05
+    m = centred_square_mask(nx, ny, D)
+    kw = dict(nu=U * D / 40.0, gamma=0.2, u_in_max=U)
+    _say("C4-shaped channel 512x128 oracle 1500 steps")
+    o = oracle.Oracle(nx, ny, channel_sides(), solid=m, **kw)
+    o.step(1500)
+    _, uo, vo = o.fields()
+    for st, tol in (("f64", 1e-11), ("f32", 1e-5)):
+        _say("C4-shaped channel", st)
+        g = lbm.Lattice(nx, ny, channel_sides(), solid=m, storage=st, check_every=100, **kw)
+        g.step(1500)
+        _, ug, vg = g.fields()
+        err = max(np.abs(ug - uo).max(), np.abs(vg - vo).max()) / U
+        _say("C4-shaped", st, "max|du|/U =", err)
+        assert err < tol, (st, err)
+        g.close()
+
+
 @pytest.mark.parametrize("sides,kw", [
     (channel_sides(), dict(nu=0.05, gamma=0.4, u_in_max=0.05)),
     (periodic_sides(), dict(nu=0.04, gamma=0.6)),

@@ -177,12 +177,15 @@ def _net_inputs(res, n, seed):
     return x0, t.astype(np.float32).astype(np.float64), (1 - solid).astype(np.uint8)
 
 
-def test_network_forward_and_gradients_match_reference(U):
+@pytest.mark.parametrize("res,n", [(16, 2), (128, 4)])
+def test_network_forward_and_gradients_match_reference(U, res, n):
+    """The whole network, forward and backward, against the NumPy FP64
+    reference with the same BF16 rounding of every activation: at 16^2
+    (batch 2) and at the deployed resolution 128^2 (batch 4)."""
     import torch
-    res, n = 16, 2
     _say("network fwd/bwd res", res, "batch", n)
     x0, t, fluid = _net_inputs(res, n, 16)
-    net = U.UNet(max_batch=4, res=res, seed=123)
+    net = U.UNet(max_batch=max(4, n), res=res, seed=123)
     params = net.params().astype(np.float64)
     out = host(net.forward(dev(x0, torch.bfloat16)))
     ref, _ = R.forward(params, x0, round_acts=True)
