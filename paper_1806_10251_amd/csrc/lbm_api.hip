@@ -1,7 +1,7 @@
 // Host side of the single-lattice C ABI declared in include/lbm.h, plus the
 // small auxiliary kernels (partial-sum finalisation, equilibrium
 // initialisation, export).  The fused step kernels live in lbm_kernels.h and
-// are instantiated per storage type in lbm_step_<type>.hip.
+// are instantiated per storage type and flavour in lbm_step.hip.
 
 #include <hip/hip_runtime.h>
 
@@ -134,6 +134,8 @@ void enqueue_step(lbm_ctx* c, hipStream_t st) {
   a.partials = c->partials;
   a.force = c->d_force ? c->d_force : c->ubuf;
   a.has_force = c->d_force != nullptr;
+  a.rng = c->rng;
+  a.rng_slot = c->cur;
   const void* src = c->lat[c->cur];
   void* dst = c->lat[c->cur ^ 1];
   int var = (c->p.strain_fd ? kVarFds : 0) | (c->p.mrt ? kVarMrt : 0);
@@ -191,6 +193,16 @@ void launch_ghost_fill(lbm_ctx* c, int which) {
                      (T*)c->lat[which], g, consts_for<C>(c), c->d_solid);
 }
 
+// The step counter of the stochastic rounding equals the step index: set it
+// wherever the state's step index is set (initialisation, checkpoint load),
+// in the slot the next step reads.
+int set_rng_counter(lbm_ctx* c) {
+  c->rng_host[c->cur] = unsigned(c->t);
+  HIPCHECK(hipMemcpyAsync(c->rng + c->cur, &c->rng_host[c->cur], sizeof(unsigned),
+                          hipMemcpyHostToDevice, c->stream));
+  return LBM_OK;
+}
+
 template <class FT>
 int init_common(lbm_ctx* c, const FT* rho, const FT* ux, const FT* uy) {
   switch (c->p.storage) {
@@ -208,7 +220,7 @@ int init_common(lbm_ctx* c, const FT* rho, const FT* ux, const FT* uy) {
       hipGraphExecDestroy(c->graph[i]);
       c->graph[i] = nullptr;
     }
-  return LBM_OK;
+  return set_rng_counter(c);
 }
 
 int export_common(lbm_ctx* c, double* pops, float* ro, float* uxo, float* uyo, double* rd,
@@ -251,6 +263,7 @@ void free_ctx(lbm_ctx* c) {
   if (c->ubuf) hipFree(c->ubuf);
   if (c->partials) hipFree(c->partials);
   if (c->result) hipFree(c->result);
+  if (c->rng) hipFree(c->rng);
   if (c->ev0) hipEventDestroy(c->ev0);
   if (c->ev1) hipEventDestroy(c->ev1);
   if (c->own_stream) hipStreamDestroy(c->own_stream);
@@ -321,6 +334,8 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid_mask, const lbm_params
   }
   ok = ok && dev(hipMalloc(&c->ubuf, 2 * n * c->csize), "hipMalloc velocity") &&
        dev(hipMalloc(&c->result, 4 * sizeof(double)), "hipMalloc result") &&
+       dev(hipMalloc(&c->rng, 2 * sizeof(unsigned)), "hipMalloc step counter") &&
+       dev(hipMemset(c->rng, 0, 2 * sizeof(unsigned)), "hipMemset step counter") &&
        dev(hipEventCreate(&c->ev0), "hipEventCreate") &&
        dev(hipEventCreate(&c->ev1), "hipEventCreate");
   if (ok && solid_mask) {
@@ -616,6 +631,9 @@ int lbm_load(lbm_ctx* c, const char* path) {
       hipGraphExecDestroy(c->graph[i]);
       c->graph[i] = nullptr;
     }
+  const int rc = set_rng_counter(c);
+  if (rc) return rc;
+  HIPCHECK(hipStreamSynchronize(c->stream));
   return LBM_OK;
 }
 

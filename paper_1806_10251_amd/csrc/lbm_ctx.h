@@ -28,6 +28,10 @@ struct lbm_ctx {
   void* ubuf = nullptr;
   double* partials = nullptr;
   double* result = nullptr;
+  // step counter of the stochastic rounding (two slots, see StepArgs::rng)
+  // and the host copy it is written from
+  unsigned* rng = nullptr;
+  unsigned rng_host[2] = {0u, 0u};
   int cur = 0;
   int64_t t = 0;
   bool checked = false;

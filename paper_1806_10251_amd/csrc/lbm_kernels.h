@@ -61,6 +61,12 @@ struct StepArgs {
                           // it unconditionally): the per-node body force when
   int has_force;          // has_force != 0, else any buffer of that size (the uniform
                           // force of the constants applies)
+  // step counter of the stochastic rounding of 16-bit storages: a kernel
+  // reads rng[rng_slot] (the step index) and one thread writes that plus one
+  // to rng[rng_slot ^ 1], the slot the next step reads (the source lattice
+  // alternates every step); nullptr for storages rounded to nearest
+  unsigned* rng;
+  int rng_slot;
 };
 
 // Blocks are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8).
@@ -93,16 +99,26 @@ __device__ __forceinline__ void finish_node(typename S::T* __restrict__ fb, cons
                                             const Consts<typename S::C>& k, const typename S::C d[9],
                                             int li, int fi, typename S::C drho,
                                             typename S::C ux, typename S::C uy, int guarded,
-                                            double acc[4]) {
+                                            double acc[4], uint32_t rng_step = 0) {
   using C = typename S::C;
   using T = typename S::T;
   const Geom& g = args.g;
   const uint32_t off = uint32_t(li) * uint32_t(sizeof(T));
   const Rsrc r = lattice_rsrc(fb);
+  if constexpr (S::kSR) {
+    // one hash of (node, step) per node; the nine seeds step through a Weyl
+    // sequence from it
+    const uint32_t h = hash32(uint32_t(li) * 0x9E3779B1u ^ hash32(rng_step));
 #pragma unroll
-  for (int a = 0; a < 9; ++a)
-    Buf<T>::template st<NTS ? 2 : 0>(r, off, uint32_t(a * g.plane) * uint32_t(sizeof(T)),
-                                     S::enc(d[a], k.scale));
+    for (int a = 0; a < 9; ++a)
+      Buf<T>::template st<NTS ? 2 : 0>(r, off, uint32_t(a * g.plane) * uint32_t(sizeof(T)),
+                                       S::enc_sr(d[a], k.scale, h + uint32_t(a) * 0x9E3779B9u));
+  } else {
+#pragma unroll
+    for (int a = 0; a < 9; ++a)
+      Buf<T>::template st<NTS ? 2 : 0>(r, off, uint32_t(a * g.plane) * uint32_t(sizeof(T)),
+                                       S::enc(d[a], k.scale));
+  }
   C* ubuf = static_cast<C*>(args.ubuf);
   const int np = g.nx * g.ny;
   if (FL == kCheck) {
@@ -240,6 +256,17 @@ __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
   const C* force = static_cast<const C*>(args.force);
   const bool has_force = args.has_force != 0;
   const int x0 = tx * kLanes;       // first column of the tile
+
+  // step index of the stochastic rounding (16-bit storages): read here, the
+  // next step's written by one thread (tile 0)
+  uint32_t rng_step = 0;
+  if constexpr (S::kSR) {
+    rng_step = __builtin_amdgcn_readfirstlane(
+        __hip_atomic_load(args.rng + args.rng_slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if (tile == 0 && lane == 0 && w == 0)
+      __hip_atomic_store(args.rng + (args.rng_slot ^ 1), rng_step + 1u, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+  }
 
   // ---- phase 1: every load of the tile is issued before any is used (one
   // memory round trip per wavefront): the own rows (nine loads per row, plus
@@ -444,8 +471,8 @@ __device__ __forceinline__ void step_tile(const typename S::T* __restrict__ fa,
     }
     C drho, ux, uy;
     const int gd = collide<C, VAR>(d[r], drx, dry, kc, fx, fy, drho, ux, uy, sxx, syy);
-    finish_node<S, FL, (VAR & kVarNts) != 0>(fb, args, kc, d[r], gidx(g, x, y), y * g.nx + x, drho, ux, uy,
-                       gd, acc);
+    finish_node<S, FL, (VAR & kVarNts) != 0>(fb, args, kc, d[r], gidx(g, x, y), y * g.nx + x,
+                                             drho, ux, uy, gd, acc, rng_step);
     // boundary slots: links whose source lies beyond a side or is a solid
     // node, populations leaving across a periodic side
     if (!INT) {

@@ -177,9 +177,13 @@ def test_residual_and_mass_match_oracle(lbm):
     assert g.guard_count == o.guard_count
 
 
-def test_checkpoint_resume_is_bit_exact(lbm, tmp_path):
-    _say("checkpoint")
-    kw = dict(nu=0.02, gamma=0.5, u_lid=0.1, storage="f32")
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_checkpoint_resume_is_bit_exact(lbm, tmp_path, storage):
+    """Save after 100 steps, load into a fresh lattice, 100 more steps: the
+    same populations as the uninterrupted run (for the 16-bit storages the
+    stochastic rounding's step counter resumes with the step index)."""
+    _say("checkpoint", storage)
+    kw = dict(nu=0.02, gamma=0.5, u_lid=0.1, storage=storage)
     a = lbm.Lattice(50, 40, cavity_sides(), **kw)
     a.step(100)
     a.save(tmp_path / "ck.bin")
@@ -189,6 +193,27 @@ def test_checkpoint_resume_is_bit_exact(lbm, tmp_path):
     assert b.steps == 100
     b.step(100)
     np.testing.assert_array_equal(a.populations(), b.populations())
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_stochastic_rounding_is_reproducible(lbm, storage):
+    """The 16-bit storages round stochastically with seeds from (node,
+    step): two lattices with the same inputs and launches store the same
+    bits, through single launches and captured graphs alike, and a
+    re-initialised lattice repeats its first run."""
+    _say("stochastic rounding reproducible", storage)
+    kw = dict(nu=0.02, gamma=0.5, u_lid=0.1, storage=storage)
+    a = lbm.Lattice(70, 45, cavity_sides(), check_every=100, **kw)
+    b = lbm.Lattice(70, 45, cavity_sides(), check_every=1, **kw)
+    a.step(350)
+    b.step(350)
+    pa = a.populations()
+    np.testing.assert_array_equal(pa, b.populations())
+    a.init_fields()
+    a.step(350)
+    np.testing.assert_array_equal(pa, a.populations())
+    a.close()
+    b.close()
 
 
 def test_device_init_matches_host_init(lbm):
@@ -212,10 +237,11 @@ def test_device_init_matches_host_init(lbm):
     np.testing.assert_allclose(out[1].cpu().numpy(), uxa, atol=1e-7)
 
 
-@pytest.mark.parametrize("storage,tol", [("bf16", 3e-2), ("f16", 3e-3)])
+@pytest.mark.parametrize("storage,tol", [("bf16", 1e-2), ("f16", 1.5e-3)])
 def test_reduced_storage_error_vs_oracle(lbm, storage, tol):
-    """BF16/FP16 deviation storage with FP32 compute: error against the FP64
-    oracle is bounded (reported, not round-off)."""
+    """BF16/FP16 deviation storage (stochastic rounding) with FP32 compute:
+    error against the FP64 oracle after 2000 steps of a 48^2 cavity, Re 100
+    (measured 4.4e-3 and 7.1e-4; round-to-nearest gave about 3x more)."""
     _say("storage", storage)
     U = 0.1
     o, g = run_pair(lbm, 48, 48, cavity_sides(), 2000, storage=storage, nu=U * 48 / 100,
@@ -282,7 +308,7 @@ def test_lattices_beyond_the_infinity_cache_against_oracle(lbm):
     assert err <= 1e-11
 
 
-@pytest.mark.parametrize("storage,tol", [("bf16", 3e-2), ("f16", 3e-3)])
+@pytest.mark.parametrize("storage,tol", [("bf16", 1e-2), ("f16", 1.5e-3)])
 def test_16bit_lattices_beyond_the_infinity_cache_against_oracle(lbm, storage, tol):
     """The 16-bit storages also switch to non-temporal population stores when
     the two lattices exceed 256 MiB (3072 x 2560: 283 MiB): all nodes after
@@ -375,9 +401,8 @@ def test_gi_shear_wave_gpu(lbm):
 def test_c4_channel_storage_precision_full_size(lbm):
     """Channel 4096 x 1024, centred square obstacle (side 128), U_max 0.05,
     Re 40 (on the obstacle side), gamma 0.2: after 4000 steps FP32 deviation
-    storage stays within 1e-5 U of FP64 storage; the 16-bit storages are
-    reported (their error is a property of the format, checked at small
-    sizes against the oracle)."""
+    storage stays within 1e-5 U of FP64 storage, FP16 (scaled, stochastic
+    rounding) within 5e-3 U and BF16 within 3e-2 U."""
     nx, ny, D, U = 4096, 1024, 128, 0.05
     from workloads import centred_square_mask
     m = centred_square_mask(nx, ny, D)
@@ -394,8 +419,11 @@ def test_c4_channel_storage_precision_full_size(lbm):
         errs[st] = max(np.abs(u - ur).max(), np.abs(v - vr).max()) / U
         g.close()
     _say("C4 max|du|/U vs FP64", errs)
+    # FP32: 8.1e-7 measured; the 16-bit storages round stochastically: FP16
+    # 1.2e-3, BF16 8.6e-3 measured (round-to-nearest gave 0.10 and 0.64)
     assert errs["f32"] < 1e-5
-    assert np.isfinite(errs["bf16"]) and np.isfinite(errs["f16"])
+    assert errs["f16"] < 5e-3
+    assert errs["bf16"] < 3e-2
 
 
 def test_c4_shaped_channel_fp32_and_fp64_against_oracle(lbm):
