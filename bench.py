@@ -220,7 +220,7 @@ def time_to_steady(lbm, n_cases, side_hi, max_steps, seed=1806, tol=1e-8):
     return out
 
 
-def batch_throughput(lbm, n_cases=256, steps=1000, seed=1806):
+def batch_throughput(lbm, n_cases=256, steps=1000, seed=1806, choice=(8, 0)):
     """The full batched mix (256 seeded cavities and channels, sides 64-512,
     FP32) for a fixed window of steps from rest: aggregate MLUPS of the batch
     against the plain driver running the cases one after another.  Lattice
@@ -238,7 +238,6 @@ def batch_throughput(lbm, n_cases=256, steps=1000, seed=1806):
     grids = [lbm.make_grid(k.nx, k.ny, k.sides) for k in cases]
     params = [lbm.make_params(storage="f32", check_every=100, **_case_kw(k)) for k in cases]
     b = lbm.Batch(grids, [k.mask for k in cases], params)
-    choice = (4, 1)
     autotune.apply_batch_choice(b, choice)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

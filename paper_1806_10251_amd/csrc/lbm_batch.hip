@@ -71,7 +71,14 @@ __device__ __forceinline__ int load_flag(const int* p) {
 constexpr int kInteriorBit = 30;
 constexpr int kTileMask = (1 << kInteriorBit) - 1;
 
-template <class S, int BY, int R, int FL, int VAR = 0>
+// Item classes of the graph schedule: each class is one launch per step, so
+// that each gets the registers of its own path (the interior path and the
+// closed-lattice boundary path fit eight blocks per compute unit; the outlet
+// path needs more).  kClsAny decides per item (the dataflow kernel).
+enum ItemClass : int { kClsInt = 0, kClsClosed = 1, kClsOutlet = 2, kClsOther = 3, kClsAny = 4 };
+constexpr int kNumClasses = 4;
+
+template <class S, int BY, int R, int FL, int VAR = 0, int CLS = kClsAny>
 __device__ __forceinline__ void run_item(const CaseDev& cd, int par, int item_tile,
                                          typename S::C (*s_rho)[kLanes + 2], double (*s_red)[4]) {
   using T = typename S::T;
@@ -79,6 +86,23 @@ __device__ __forceinline__ void run_item(const CaseDev& cd, int par, int item_ti
   const T* fa = static_cast<const T*>(cd.lat[par]);
   T* fb = static_cast<T*>(cd.lat[par ^ 1]);
   const int tile = item_tile & kTileMask;
+  if constexpr (CLS == kClsInt) {
+    step_tile<S, BY, R, FL, false, false, VAR, true>(fa, fb, cd.a[par], case_consts<C>(cd), tile,
+                                                     s_rho, s_red);
+    return;
+  } else if constexpr (CLS == kClsClosed) {
+    step_tile<S, BY, R, FL, true, false, VAR, false, true>(fa, fb, cd.a[par], case_consts<C>(cd),
+                                                           tile, s_rho, s_red);
+    return;
+  } else if constexpr (CLS == kClsOutlet) {
+    step_tile<S, BY, R, FL, true, true, VAR>(fa, fb, cd.a[par], case_consts<C>(cd), tile, s_rho,
+                                             s_red);
+    return;
+  } else if constexpr (CLS == kClsOther) {
+    step_tile<S, BY, R, FL, true, false, VAR>(fa, fb, cd.a[par], case_consts<C>(cd), tile, s_rho,
+                                              s_red);
+    return;
+  }
   if (item_tile >> kInteriorBit)
     step_tile<S, BY, R, FL, false, false, VAR, true>(fa, fb, cd.a[par], case_consts<C>(cd), tile,
                                                      s_rho, s_red);
@@ -182,14 +206,15 @@ struct StepLaunch {
 
 // NTS: non-temporal population stores (the active lattices together exceed
 // the last-level cache).
-template <class S, int BY, int R, int FL, bool NTS>
+template <class S, int BY, int R, int FL, bool NTS, int CLS>
 __global__ __launch_bounds__(kLanes* BY) void batch_step_kernel(StepLaunch L) {
   __shared__ typename S::C s_rho[BY * R + 2][kLanes + 2];
   __shared__ double s_red[BY][4];
   const int it = xcd_tile(blockIdx.x, L.n_items);
   const int c = L.item_case[it];
   if (!L.active[c]) return;
-  run_item<S, BY, R, FL, NTS ? kVarNts : 0>(L.cases[c], L.par, L.item_tile[it], s_rho, s_red);
+  run_item<S, BY, R, FL, NTS ? kVarNts : 0, CLS>(L.cases[c], L.par, L.item_tile[it], s_rho,
+                                                 s_red);
 }
 
 // one block per case: residual of the check step that ends the window
@@ -321,6 +346,8 @@ struct lbm_batch {
   int* d_item_case = nullptr;
   int* d_item_tile = nullptr;
   int n_items = 0, item_cap = 0;
+  int cls_off[kNumClasses + 1] = {0, 0, 0, 0, 0};  // graph schedule: items of class k
+                                                   // are [cls_off[k], cls_off[k + 1])
   double* d_partials = nullptr;
   double* d_case_res = nullptr;
   int* d_active = nullptr;
@@ -443,26 +470,41 @@ int rebuild_items(lbm_batch* b) {
   drop_graphs(b);
   // ticket order within a step: schedule 0 = case by case (a case's tiles
   // contiguous), 1 = tiles interleaved across cases
+  // the graph schedules group the items by class (one launch per class and
+  // step); the dataflow schedule keeps one list
   std::vector<int> ic, itl;
-  if (b->schedule == 0) {
-    for (int i = 0; i < b->n; ++i) {
-      if (!b->h_active[i]) continue;
-      for (int t = 0; t < b->cs[i].ntiles; ++t) {
-        ic.push_back(i);
-        itl.push_back(t | (int(b->cs[i].tile_int[t]) << kInteriorBit));
+  auto item_class = [&](int i, int t) {
+    if (b->cs[i].tile_int[t]) return int(kClsInt);
+    const int32_t* sd = b->cs[i].grid.side;
+    if (sd[1] == LBM_SIDE_OUTLET) return int(kClsOutlet);
+    bool closed = true;
+    for (int q = 0; q < 4; ++q)
+      closed = closed && (sd[q] == LBM_SIDE_WALL || sd[q] == LBM_SIDE_LID);
+    return int(closed ? kClsClosed : kClsOther);
+  };
+  const int ncls = b->schedule == 2 ? 1 : kNumClasses;
+  for (int k = 0; k < ncls; ++k) {
+    b->cls_off[k] = (int)ic.size();
+    auto take = [&](int i, int t) {
+      if (ncls > 1 && item_class(i, t) != k) return;
+      ic.push_back(i);
+      itl.push_back(t | (int(b->cs[i].tile_int[t]) << kInteriorBit));
+    };
+    if (b->schedule != 1) {
+      for (int i = 0; i < b->n; ++i) {
+        if (!b->h_active[i]) continue;
+        for (int t = 0; t < b->cs[i].ntiles; ++t) take(i, t);
       }
-    }
-  } else {
-    int maxt = 0;
-    for (int i = 0; i < b->n; ++i)
-      if (b->h_active[i]) maxt = std::max(maxt, b->cs[i].ntiles);
-    for (int t = 0; t < maxt; ++t)
+    } else {
+      int maxt = 0;
       for (int i = 0; i < b->n; ++i)
-        if (b->h_active[i] && t < b->cs[i].ntiles) {
-          ic.push_back(i);
-          itl.push_back(t | (int(b->cs[i].tile_int[t]) << kInteriorBit));
-        }
+        if (b->h_active[i]) maxt = std::max(maxt, b->cs[i].ntiles);
+      for (int t = 0; t < maxt; ++t)
+        for (int i = 0; i < b->n; ++i)
+          if (b->h_active[i] && t < b->cs[i].ntiles) take(i, t);
+    }
   }
+  for (int k = ncls; k <= kNumClasses; ++k) b->cls_off[k] = (int)ic.size();
   b->n_items = (int)ic.size();
   if (b->n_items > b->item_cap) {
     hipFree(b->d_item_case);
@@ -528,28 +570,39 @@ int align_parity(lbm_batch* b) {
 }
 
 
-template <class S, int BY, bool NTS>
-void launch_step_nts(int flavor, const StepLaunch& L, hipStream_t st) {
+template <class S, int BY, bool NTS, int CLS>
+void launch_step_cls(int flavor, const StepLaunch& L, hipStream_t st) {
   dim3 grid(L.n_items), block(kLanes, BY);
   if (flavor == kCheck)
-    hipLaunchKernelGGL((batch_step_kernel<S, BY, 1, kCheck, NTS>), grid, block, 0, st, L);
+    hipLaunchKernelGGL((batch_step_kernel<S, BY, 1, kCheck, NTS, CLS>), grid, block, 0, st, L);
   else if (flavor == kStore)
-    hipLaunchKernelGGL((batch_step_kernel<S, BY, 1, kStore, NTS>), grid, block, 0, st, L);
+    hipLaunchKernelGGL((batch_step_kernel<S, BY, 1, kStore, NTS, CLS>), grid, block, 0, st, L);
   else
-    hipLaunchKernelGGL((batch_step_kernel<S, BY, 1, kPlain, NTS>), grid, block, 0, st, L);
+    hipLaunchKernelGGL((batch_step_kernel<S, BY, 1, kPlain, NTS, CLS>), grid, block, 0, st, L);
+}
+
+template <class S, int BY, bool NTS>
+void launch_step_nts(int flavor, int cls, const StepLaunch& L, hipStream_t st) {
+  switch (cls) {
+    case kClsInt: launch_step_cls<S, BY, NTS, kClsInt>(flavor, L, st); break;
+    case kClsClosed: launch_step_cls<S, BY, NTS, kClsClosed>(flavor, L, st); break;
+    case kClsOutlet: launch_step_cls<S, BY, NTS, kClsOutlet>(flavor, L, st); break;
+    default: launch_step_cls<S, BY, NTS, kClsOther>(flavor, L, st); break;
+  }
 }
 
 template <class S, int BY>
-void launch_step_by(int flavor, bool nts, const StepLaunch& L, hipStream_t st) {
-  if (nts) launch_step_nts<S, BY, true>(flavor, L, st);
-  else launch_step_nts<S, BY, false>(flavor, L, st);
+void launch_step_by(int flavor, int cls, bool nts, const StepLaunch& L, hipStream_t st) {
+  if (nts) launch_step_nts<S, BY, true>(flavor, cls, L, st);
+  else launch_step_nts<S, BY, false>(flavor, cls, L, st);
 }
 
 template <class S>
-void launch_step_storage(int by, int flavor, bool nts, const StepLaunch& L, hipStream_t st) {
-  if (by == 8) launch_step_by<S, 8>(flavor, nts, L, st);
-  else if (by == 16) launch_step_by<S, 16>(flavor, nts, L, st);
-  else launch_step_by<S, 4>(flavor, nts, L, st);
+void launch_step_storage(int by, int flavor, int cls, bool nts, const StepLaunch& L,
+                         hipStream_t st) {
+  if (by == 8) launch_step_by<S, 8>(flavor, cls, nts, L, st);
+  else if (by == 16) launch_step_by<S, 16>(flavor, cls, nts, L, st);
+  else launch_step_by<S, 4>(flavor, cls, nts, L, st);
 }
 
 // Bytes of the two lattices of every active case.  Beyond the 256 MiB
@@ -597,9 +650,16 @@ void enqueue_window(lbm_batch* b, long long t, int nsteps, const RetireArgs& r, 
     const long long idx = (tt + 1) % b->K;
     const int flavor = idx == 0 ? kCheck : ((b->K >= 2 && idx == b->K - 1) ? kStore : kPlain);
     L.par = int(tt & 1);
-    if (L.n_items > 0) {
-      if (b->storage == LBM_STORE_F64) launch_step_storage<StoreF64>(b->by, flavor, nts, L, st);
-      else launch_step_storage<StoreF32>(b->by, flavor, nts, L, st);
+    for (int k = 0; k < kNumClasses; ++k) {
+      StepLaunch Lk = L;
+      Lk.item_case = b->d_item_case + b->cls_off[k];
+      Lk.item_tile = b->d_item_tile + b->cls_off[k];
+      Lk.n_items = b->cls_off[k + 1] - b->cls_off[k];
+      if (Lk.n_items <= 0) continue;
+      if (b->storage == LBM_STORE_F64)
+        launch_step_storage<StoreF64>(b->by, flavor, k, nts, Lk, st);
+      else
+        launch_step_storage<StoreF32>(b->by, flavor, k, nts, Lk, st);
     }
     last_flavor = flavor;
   }
