@@ -86,21 +86,23 @@ __device__ __forceinline__ void run_item(const CaseDev& cd, int par, int item_ti
   const T* fa = static_cast<const T*>(cd.lat[par]);
   T* fb = static_cast<T*>(cd.lat[par ^ 1]);
   const int tile = item_tile & kTileMask;
+  // the case's step arguments and constants as local (scalar) copies, read
+  // before the first population load: read where used, a field needed for
+  // an address after the population loads are issued costs a second round
+  // trip (its load waits for every load before it)
+  const StepArgs args = cd.a[par];
+  const Consts<C> k = case_consts<C>(cd);
   if constexpr (CLS == kClsInt) {
-    step_tile<S, BY, R, FL, false, false, VAR, true>(fa, fb, cd.a[par], case_consts<C>(cd), tile,
-                                                     s_rho, s_red);
+    step_tile<S, BY, R, FL, false, false, VAR, true>(fa, fb, args, k, tile, s_rho, s_red);
     return;
   } else if constexpr (CLS == kClsClosed) {
-    step_tile<S, BY, R, FL, true, false, VAR, false, true>(fa, fb, cd.a[par], case_consts<C>(cd),
-                                                           tile, s_rho, s_red);
+    step_tile<S, BY, R, FL, true, false, VAR, false, true>(fa, fb, args, k, tile, s_rho, s_red);
     return;
   } else if constexpr (CLS == kClsOutlet) {
-    step_tile<S, BY, R, FL, true, true, VAR>(fa, fb, cd.a[par], case_consts<C>(cd), tile, s_rho,
-                                             s_red);
+    step_tile<S, BY, R, FL, true, true, VAR>(fa, fb, args, k, tile, s_rho, s_red);
     return;
   } else if constexpr (CLS == kClsOther) {
-    step_tile<S, BY, R, FL, true, false, VAR>(fa, fb, cd.a[par], case_consts<C>(cd), tile, s_rho,
-                                              s_red);
+    step_tile<S, BY, R, FL, true, false, VAR>(fa, fb, args, k, tile, s_rho, s_red);
     return;
   }
   if (item_tile >> kInteriorBit)
