@@ -402,6 +402,7 @@ struct Wgrad2Args {
   const bf16* dyT;    // [cout][npix]
   const bf16* xT;     // [cin][npix]
   float* part;        // [splits][cout][9][cin]
+  float* bpart;       // [splits][cout] (bias partial sums) or null
   int npix, npad, h, wd, cin, cout, chunk;
 };
 
@@ -436,8 +437,13 @@ __device__ __forceinline__ bf16x8 tap_row8(const bf16* __restrict__ row, int p, 
   return o;
 }
 
+// One block: a 32 x 32 tile of one tap over one pixel chunk (split); its
+// partial sum goes to `part`.  The blocks of the centre tap and the first
+// input-channel tile also sum dy over their chunk for the bias gradient
+// (`bpart`), so the bias needs no launch of its own.
 __global__ __launch_bounds__(256) void wgrad2_kernel(Wgrad2Args a) {
   __shared__ float sR[4][32][33];
+  __shared__ float sB[256];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   int bid = blockIdx.x;
   const int t = bid % 9;
@@ -479,36 +485,34 @@ __global__ __launch_bounds__(256) void wgrad2_kernel(Wgrad2Args a) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) sR[wv][16 * i + 4 * g + v][16 * j + r] = acc[i][j][v];
   __syncthreads();
+  const long long wcount = 9LL * a.cin * a.cout;
   for (int e = threadIdx.x; e < 1024; e += 256) {
     const int co = e >> 5, ci = e & 31;
     const float s = sR[0][co][ci] + sR[1][co][ci] + sR[2][co][ci] + sR[3][co][ci];
-    a.part[(((long long)blockIdx.y * a.cout + co0 + co) * 9 + t) * a.cin + ci0 + ci] = s;
+    a.part[blockIdx.y * wcount + ((long long)(co0 + co) * 9 + t) * a.cin + ci0 + ci] = s;
   }
-}
-
-// bias partials: bpart[s][co] = sum of dy over the pixels of split s; one
-// block per (channel, split), 8 pixels per load, fixed-order tree in LDS
-__global__ __launch_bounds__(256) void bias_partial_kernel(const bf16* __restrict__ dyT, int npad,
-                                                           int npix, int chunk, int cout,
-                                                           float* __restrict__ bpart) {
-  __shared__ float sm[256];
-  const int co = blockIdx.x;
-  const int pbeg = blockIdx.y * chunk, pend = min(npix, pbeg + chunk);
-  const bf16* row = dyT + (long long)co * npad;
-  float s = 0.f;
-  for (int p = pbeg + 8 * (int)threadIdx.x; p < pend; p += 8 * 256) {
-    const bf16x8 v = *reinterpret_cast<const bf16x8*>(row + p);
+  const bool bias_tile = a.bpart != nullptr && t == 4 && ci0 == 0;
+  if (bias_tile) {
+    // eight threads per output channel, 8 pixels per load, fixed order
+    const int co = threadIdx.x >> 3, l8 = threadIdx.x & 7;
+    const bf16* row = a.dyT + (long long)(co0 + co) * a.npad;
+    const int pend = min(a.npix, pbeg + a.chunk);
+    float s = 0.f;
+    for (int p = pbeg + 8 * l8; p < pend; p += 64) {
+      const bf16x8 v = *reinterpret_cast<const bf16x8*>(row + p);
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (p + u < pend) s += (float)v[u];
-  }
-  sm[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+      for (int u = 0; u < 8; ++u)
+        if (p + u < pend) s += (float)v[u];
+    }
+    sB[threadIdx.x] = s;
     __syncthreads();
+    if (l8 == 0) {
+      float b = 0.f;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) b += sB[threadIdx.x + u];
+      a.bpart[(long long)blockIdx.y * a.cout + co0 + co] = b;
+    }
   }
-  if (threadIdx.x == 0) bpart[(long long)blockIdx.y * cout + co] = sm[0];
 }
 
 // out[i] = sum_s part[s][i] (fixed order)
@@ -518,6 +522,26 @@ __global__ void sum_splits_kernel(const float* part, long long count, int splits
     float s = 0.f;
     for (int k = 0; k < splits; ++k) s += part[(long long)k * count + i];
     out[i] = s;
+  }
+}
+
+// Both sums of the weight gradient in one launch: out[i] = sum_s part[s][i]
+// for i < count and bout[j] = sum_s bpart[s][j] for j < bcount (bpart may be
+// null), each in split order.
+__global__ void sum_splits2_kernel(const float* part, long long count, const float* bpart,
+                                   int bcount, int splits, float* out, float* bout) {
+  const long long total = count + (bpart ? bcount : 0);
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    float s = 0.f;
+    if (i < count) {
+      for (int k = 0; k < splits; ++k) s += part[(long long)k * count + i];
+      out[i] = s;
+    } else {
+      const long long j = i - count;
+      for (int k = 0; k < splits; ++k) s += bpart[(long long)k * bcount + j];
+      bout[j] = s;
+    }
   }
 }
 
@@ -951,23 +975,17 @@ int unet_conv3x3_bwd_weight(const void* dy, int32_t lddy, const void* x, int32_t
     const long long used = ((long long)splits * (wcount + cout) + 63) / 64 * 64;
     bf16* dyT = reinterpret_cast<bf16*>(work + used);
     bf16* xT = dyT + (long long)cout * npad;
+    const int tiles = (cout / 32) * (cin / 32) * 9;
     hipLaunchKernelGGL(to_channel_major_kernel, dim3((npix + 63) / 64, cout / 32), dim3(256), 0,
                        st, static_cast<const bf16*>(dy), lddy, dyT, npix, npad);
     hipLaunchKernelGGL(to_channel_major_kernel, dim3((npix + 63) / 64, cin / 32), dim3(256), 0,
                        st, static_cast<const bf16*>(x), ldx, xT, npix, npad);
     UCHECK(hipGetLastError());
-    Wgrad2Args a2{dyT, xT, part, npix, npad, h, wd, cin, cout, chunk};
-    hipLaunchKernelGGL(wgrad2_kernel, dim3((cout / 32) * (cin / 32) * 9, splits), dim3(256), 0,
-                       st, a2);
-    if (dbias)
-      hipLaunchKernelGGL(bias_partial_kernel, dim3(cout, splits), dim3(256), 0, st, dyT, npad,
-                         npix, chunk, cout, bpart);
+    Wgrad2Args a2{dyT, xT, part, dbias ? bpart : nullptr, npix, npad, h, wd, cin, cout, chunk};
+    hipLaunchKernelGGL(wgrad2_kernel, dim3(tiles, splits), dim3(256), 0, st, a2);
     UCHECK(hipGetLastError());
-    hipLaunchKernelGGL(sum_splits_kernel, dim3(grid_for(wcount)), dim3(256), 0, st, part, wcount,
-                       splits, dw);
-    if (dbias)
-      hipLaunchKernelGGL(sum_splits_kernel, dim3(grid_for(cout)), dim3(256), 0, st, bpart,
-                         (long long)cout, splits, dbias);
+    hipLaunchKernelGGL(sum_splits2_kernel, dim3(grid_for(wcount + cout)), dim3(256), 0, st, part,
+                       wcount, dbias ? bpart : nullptr, cout, splits, dw, dbias);
     UCHECK(hipGetLastError());
     return UNET_OK;
   }

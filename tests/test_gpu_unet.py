@@ -106,6 +106,37 @@ def test_conv_backward_weight(U, n, h, w, cin, cout):
     assert (np.abs(host(db) - db_ref) <= 1e-5 * np.abs(dy).reshape(-1, cout).sum(0) + 1e-6).all()
 
 
+def test_conv_backward_weight_work_reuse(U):
+    """Two weight-gradient calls in a row on one work buffer that starts out
+    as garbage (NaN bit patterns): the per-tile counters the kernel uses to
+    pick the block that adds up the split partials are cleared by each call,
+    and dbias may be absent."""
+    import torch
+    _say("conv bwd weight, work reuse")
+    rng = np.random.default_rng(13)
+    shapes = [(4, 64, 64, 32, 64), (2, 16, 16, 64, 32)]
+    nw = max(int(U.load().unet_wgrad_work_floats(n, h, w, ci, co)) for n, h, w, ci, co in shapes)
+    work = torch.full((nw,), float("nan"), device="cuda", dtype=torch.float32)
+    for k, (n, h, w, cin, cout) in enumerate(shapes):
+        dy = bf(rng, n, h, w, cout)
+        x = bf(rng, n, h, w, cin)
+        dw_ref, db_ref = R.conv3x3_bwd_weight(dy, x)
+        bound, _ = R.conv3x3_bwd_weight(np.abs(dy), np.abs(x))
+        dyd, xd = dev(dy, torch.bfloat16), dev(x, torch.bfloat16)
+        dw = torch.empty((cout, 9, cin), device="cuda", dtype=torch.float32)
+        db = torch.empty(cout, device="cuda", dtype=torch.float32)
+        with_bias = k == 0
+        rc = U.load().unet_conv3x3_bwd_weight(U._p(dyd), cout, U._p(xd), cin, U._p(dw),
+                                              U._p(db) if with_bias else None, n, h, w, cin,
+                                              cout, U._p(work), U._stream())
+        assert rc == 0
+        torch.cuda.synchronize()
+        assert (np.abs(host(dw) - dw_ref) <= 1e-5 * bound + 1e-6).all()
+        if with_bias:
+            assert (np.abs(host(db) - db_ref) <= 1e-5 * np.abs(dy).reshape(-1, cout).sum(0)
+                    + 1e-6).all()
+
+
 def test_pool_upsample_relu(U):
     import torch
     rng = np.random.default_rng(13)
