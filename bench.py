@@ -61,6 +61,72 @@ def cpu_baseline(n, U, re, gamma, budget_s=12.0):
                               "sample": f"{steps1} further steps, {el1:.1f} s"}}
 
 
+
+def _host_cpu():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_plan(progress=None):
+    """The FP64 oracle over the host-baseline runs: lid-driven cavities of 256^2
+    and 1024^2 for 1000 fixed steps at gamma 0.5 (Re 1000, U_lid 0.1), on one
+    thread and on all threads (1024^2 on one thread: a 100-step sample); a
+    128^2 cavity at Re 100, U_lid 0.1 run from rest to a velocity residual
+    below 1e-8 (checked every 100 steps) at gamma 1 and 0.5; and the 32^2
+    cavity at Re 100, gamma 0.5, 5000 steps (wall time)."""
+    import oracle
+    from workloads import cavity_sides
+
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    say = progress or (lambda m: None)
+
+    def fixed(n, re, gamma, steps, threads):
+        oracle.set_threads(threads)
+        o = oracle.Oracle(n, n, cavity_sides(), nu=0.1 * n / re, gamma=gamma, u_lid=0.1)
+        o.step(2)
+        t0 = time.perf_counter()
+        o.step(steps)
+        el = time.perf_counter() - t0
+        o.close()
+        say(f"cavity {n}^2 {steps} steps, {threads} threads: {el:.2f} s")
+        return {"n": n, "re": re, "gamma": gamma, "steps": steps, "threads": threads,
+                "seconds": round(el, 3), "mlups": round(n * n * steps / el / 1e6, 2)}
+
+    def to_steady(n, re, gamma, threads, tol=1e-8, every=100, cap=2_000_000):
+        oracle.set_threads(threads)
+        o = oracle.Oracle(n, n, cavity_sides(), nu=0.1 * n / re, gamma=gamma, u_lid=0.1)
+        t0 = time.perf_counter()
+        steps = 0
+        res = float("inf")
+        while steps < cap:
+            o.step(every)
+            steps += every
+            res = o.residual
+            if res < tol:
+                break
+        el = time.perf_counter() - t0
+        o.close()
+        say(f"cavity {n}^2 gamma {gamma} to {tol:g}: {steps} steps, {el:.1f} s")
+        return {"n": n, "re": re, "gamma": gamma, "tol": tol, "check_every": every,
+                "threads": threads, "steps": steps, "converged": bool(res < tol),
+                "residual": res, "seconds": round(el, 2),
+                "mlups": round(n * n * steps / el / 1e6, 2)}
+
+    out = {"host_cpu": _host_cpu(), "threads_all": cores, "kind": "oracle", "storage": "f64"}
+    out["fixed_steps"] = [fixed(256, 1000, 0.5, 1000, 1), fixed(256, 1000, 0.5, 1000, cores),
+                          fixed(1024, 1000, 0.5, 100, 1), fixed(1024, 1000, 0.5, 1000, cores)]
+    out["time_to_steady"] = [to_steady(128, 100, g, cores) for g in (1.0, 0.5)]
+    out["c1_wall"] = [fixed(32, 100, 0.5, 5000, 1), fixed(32, 100, 0.5, 5000, cores)]
+    oracle.set_threads(cores)
+    return out
+
+
 # Kernel sources and the build script (its compile flags) for which the
 # committed traffic summary holds HBM byte counters; the figure is reported
 # only while their hash matches.
@@ -208,7 +274,8 @@ def time_to_steady(lbm, n_cases, side_hi, max_steps, seed=1806, tol=1e-8):
                              "speedup_vs_plain": round(t_plain / sec, 3)}
     if net is not None:
         out["warm_start"] = {"weights": os.path.relpath(WEIGHTS, ROOT),
-                             "covers": "square cavities (channels keep the cold start)",
+                             "covers": "square cavities (channels keep the cold start; a warm start that "
+                                       "diverges runs again from rest within the arm)",
                              "filter_steps": list(surrogate.WARM_FILTER),
                              "tol": tol / 10,
                              "note": "accuracy-matched arm: error against the reference at "
@@ -311,6 +378,10 @@ def main():
                     help="skip the fixed-window throughput of the 256-case batch")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip timing the uncorrected (eq. 4) and finite-difference-strain kernels")
+    ap.add_argument("--cpu-plan", action="store_true",
+                    help="only time the FP64 oracle on this host over the host-baseline runs "
+                         "(fixed-step cavities, 128^2 time to steady state, the 32^2 case) and "
+                         "print them as one JSON line; no GPU is used")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 256 MiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -319,6 +390,11 @@ def main():
         print(f"bench.py: --gpus {args.gpus} is not supported; this build runs the method on one "
               "GPU (multi-GPU sharding is design-only).", file=sys.stderr)
         sys.exit(2)
+
+    if args.cpu_plan:
+        print(json.dumps({"cpu_plan": cpu_plan(
+            lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))}), flush=True)
+        return
 
     import torch
 

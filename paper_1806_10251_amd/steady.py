@@ -95,7 +95,9 @@ def batch_arm(cases, tol, max_steps, storage="f64", choice=None, warm_net=None, 
     network's prediction, computed inside the timed region), with optional
     filter steps.  segment: run in windows of that many steps (a multiple of
     the check cadence), retiring finished cases between windows and logging
-    each window.  Returns (steps, status, seconds, [(ux, uy)] per case)."""
+    each window.  With the warm start, a predicted case that diverges is run
+    again from rest (the cold start is the fallback), inside the arm's time.
+    Returns (steps, status, seconds, [(ux, uy)] per case)."""
     import torch
 
     from . import autotune, surrogate
@@ -142,6 +144,22 @@ def batch_arm(cases, tol, max_steps, storage="f64", choice=None, warm_net=None, 
     sec = time.perf_counter() - t0
     fields = [b.fields(i, k.ny, k.nx)[1:] for i, k in enumerate(cases)]
     b.close()
+    if warm_net is not None:
+        # the cold start is the fallback: a warm-started case that diverges
+        # runs again from rest (same filter); its steps and the time of the
+        # second run are added to the arm
+        redo = [i for i, k in enumerate(cases) if surrogate.covers(k) and st[i] == 3]
+        if redo:
+            if log:
+                log(f"[tts] {len(redo)} warm-started case(s) diverged; rerun from rest")
+            steps2, st2, sec2, fields2 = batch_arm([cases[i] for i in redo], tol, max_steps,
+                                                   storage, choice, None, filter_at, plateau,
+                                                   segment, log)
+            for j, i in enumerate(redo):
+                total[i] += steps2[j]
+                st[i] = st2[j]
+                fields[i] = fields2[j]
+            sec += sec2
     return total, st, sec, fields
 
 

@@ -317,3 +317,34 @@ def test_held_out_cold_versus_warm_start(U):
     assert (stc == 1).all() and (stw == 1).all()
     assert ec < 1e-3 and ew < 1e-3
     assert sw.sum() <= 1.1 * sc.sum()
+
+
+def test_diverging_warm_start_falls_back_to_the_cold_start(U):
+    """A case whose warm start diverges (cavity 108^2, Re 535, gamma 0.087,
+    U 0.038 of the seeded 24-case sample: the predicted field at this
+    pseudo-Mach number blows up within 100 steps, while the cold start stays
+    finite) is run again from rest inside the same arm: its status and
+    fields are those of the cold run, and its steps include the failed
+    attempt."""
+    import os
+    from paper_1806_10251_amd import steady as SD
+    from paper_1806_10251_amd import surrogate as S
+    from workloads import draw_cases
+    if not os.path.exists(S.DEFAULT_WEIGHTS):
+        pytest.skip("no trained weights")
+    k = draw_cases(24, 1806, side_lo=64, side_hi=128)[16]
+    assert k.kind == "cavity" and k.nx == 108 and S.covers(k)
+    net = U.UNet(max_batch=4, res=S.RES, seed=0)
+    S.load_into(net, S.DEFAULT_WEIGHTS)
+    _say("fallback case", k.nx, k.re, k.gamma, k.u_ref)
+    cap = 3000
+    sc, stc, _, fc = SD.batch_arm([k], 1e-8, cap, "f64", filter_at=S.WARM_FILTER)
+    sw, stw, _, fw = SD.batch_arm([k], 1e-8, cap, "f64", warm_net=net, filter_at=S.WARM_FILTER)
+    net.close()
+    _say("cold", int(sc[0]), int(stc[0]), "warm with fallback", int(sw[0]), int(stw[0]))
+    assert int(stc[0]) != 3                      # the cold start stays finite
+    assert int(stw[0]) == int(stc[0])            # the fallback ends as the cold run does
+    assert int(sw[0]) > int(sc[0])               # and pays for the failed attempt
+    for a, b in zip(fc[0], fw[0]):
+        assert np.isfinite(b).all()
+        assert np.array_equal(a, b)              # the same cold run, bit for bit
