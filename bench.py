@@ -177,7 +177,12 @@ def timed_window(warmup, steps, K):
             "check_every": K, "graph_windows": "captured graphs of K steps, replayed"}
 
 
-WEIGHTS = os.path.join(ROOT, "paper_1806_10251_amd", "weights", "unet_cavity128.npy")
+def _default_weights():
+    from paper_1806_10251_amd import surrogate
+    return surrogate.DEFAULT_WEIGHTS
+
+
+WEIGHTS = None   # set in time_to_steady (the library's default weights)
 
 
 def _case_kw(k):
@@ -226,6 +231,8 @@ def time_to_steady(lbm, n_cases, side_hi, max_steps, seed=1806, tol=1e-8):
                                       filter_at=surrogate.WARM_FILTER)
     arms["batch+filter@tol/10"] = _batch_arm(lbm, cases, choice, tol / 10, max_steps,
                                              filter_at=surrogate.WARM_FILTER)
+    global WEIGHTS
+    WEIGHTS = _default_weights()
     net = None
     if os.path.exists(WEIGHTS):
         net = U.UNet(max_batch=16, res=surrogate.RES, seed=0)
@@ -273,9 +280,11 @@ def time_to_steady(lbm, n_cases, side_hi, max_steps, seed=1806, tol=1e-8):
                              "max_err": _accuracy(cases, flds, f_ref, [i for i in ok if st[i] == 1]),
                              "speedup_vs_plain": round(t_plain / sec, 3)}
     if net is not None:
+        kinds = getattr(net, "kinds", ("cavity",))
         out["warm_start"] = {"weights": os.path.relpath(WEIGHTS, ROOT),
-                             "covers": "square cavities (channels keep the cold start; a warm start that "
-                                       "diverges runs again from rest within the arm)",
+                             "covers": ", ".join(kinds) + " (other cases keep the cold start; a "
+                                       "warm start that diverges runs again from rest within "
+                                       "the arm)",
                              "filter_steps": list(surrogate.WARM_FILTER),
                              "tol": tol / 10,
                              "note": "accuracy-matched arm: error against the reference at "

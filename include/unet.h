@@ -36,6 +36,9 @@ enum { UNET_OK = 0, UNET_EINVAL = -1, UNET_ENOMEM = -2, UNET_EDEVICE = -3 };
 #define UNET_IN_CHANNELS 32
 #define UNET_OUT_CHANNELS 32
 
+/* Case kinds of the rectangular input/output maps (case_params[i][3]). */
+enum { UNET_KIND_CAVITY = 0, UNET_KIND_CHANNEL = 1 };
+
 /* ---------------------------------------------------------------------- */
 /* Layer kernels (stateless)                                               */
 /* ---------------------------------------------------------------------- */
@@ -125,6 +128,23 @@ int unet_make_input(const uint8_t* solid, int32_t fine, const float* case_params
 int unet_fields_from_output(const float* out, int32_t ldo, int32_t n, int32_t res,
                             const float* case_params, const uint8_t* solid, int32_t fine,
                             float* rho, float* ux, float* uy, void* stream);
+
+/* The same two maps for lattices of nx x ny nodes (cavities and channels
+ * alike): solid is u8 [n][ny][nx]; case_params[i] = {Re, gamma, U, kind}
+ * (FP32, device; kind UNET_KIND_CAVITY or UNET_KIND_CHANNEL, as a float).
+ * Coarse cells cover floor(I nx/res) .. floor((I+1) nx/res) - 1 along x and
+ * likewise along y with ny.  Channel 6 of the input marks the driven
+ * boundary: the top row of a cavity (lid), the left column of a channel
+ * (inlet).  The fields of a cavity are corrected as above; those of a
+ * channel (its inlet and outlet change the mass, and it keeps no staggered
+ * sums) are the interpolated prediction as it is.  rho, ux, uy: FP32 device
+ * [n][ny][nx].  With square lattices and kind 0 the results equal those of
+ * unet_make_input and unet_fields_from_output. */
+int unet_make_input_rect(const uint8_t* solid, int32_t nx, int32_t ny, const float* case_params,
+                         int32_t n, int32_t res, void* x0, void* stream);
+int unet_fields_from_output_rect(const float* out, int32_t ldo, int32_t n, int32_t res,
+                                 const float* case_params, const uint8_t* solid, int32_t nx,
+                                 int32_t ny, float* rho, float* ux, float* uy, void* stream);
 
 /* ---------------------------------------------------------------------- */
 /* The network: 4 levels, 32/64/128/256 channels, two 3x3 convolutions      */

@@ -225,13 +225,31 @@ def backward(params, x0, target, fluid, round_acts=False):
     return loss, flat
 
 
+KIND_CAVITY, KIND_CHANNEL = 0, 1
+
+
+def _kinds(case_params):
+    cp = np.asarray(case_params, np.float64)
+    if cp.shape[1] > 3:
+        return cp[:, 3].astype(int)
+    return np.full(cp.shape[0], KIND_CAVITY)
+
+
 def make_input(solid, case_params, res):
-    """Network input as defined for the device (channels 0-7 used)."""
+    """Network input as defined for the device (channels 0-7 used).  solid
+    [n][ny][nx]; case_params rows (Re, gamma, U) for cavities or
+    (Re, gamma, U, kind).  Channel 6 marks the driven boundary: the top row
+    of a cavity, the left column of a channel."""
     solid = np.asarray(solid)
-    n, fine, _ = solid.shape
-    lo = [I * fine // res for I in range(res)]
-    hi = [max((I + 1) * fine // res, lo[I] + 1) for I in range(res)]
-    frac = np.array([[[solid[k, lo[J]:hi[J], lo[I]:hi[I]].astype(np.float64).mean()
+    n, ny, nx = solid.shape
+
+    def cells(fine):
+        lo = [I * fine // res for I in range(res)]
+        hi = [max((I + 1) * fine // res, lo[I] + 1) for I in range(res)]
+        return lo, hi
+    lx, hx = cells(nx)
+    ly, hy = cells(ny)
+    frac = np.array([[[solid[k, ly[J]:hy[J], lx[I]:hx[I]].astype(np.float64).mean()
                        for I in range(res)] for J in range(res)] for k in range(n)])
     x = np.zeros((n, res, res, IN_CHANNELS))
     cp = np.asarray(case_params, np.float64)
@@ -242,7 +260,11 @@ def make_input(solid, case_params, res):
     x[..., 3] = cp[:, 2, None, None] / 0.1
     x[..., 4] = c[None, None, :]
     x[..., 5] = c[None, :, None]
-    x[:, res - 1, :, 6] = 1.0
+    for k, kind in enumerate(_kinds(case_params)):
+        if kind == KIND_CHANNEL:
+            x[k, :, 0, 6] = 1.0
+        else:
+            x[k, res - 1, :, 6] = 1.0
     x[..., 7] = 1.0
     return x
 
@@ -250,38 +272,44 @@ def make_input(solid, case_params, res):
 def fields_from_output(out, case_params, solid):
     """Lattice fields from the network output: bilinear interpolation of the
     coarse pixel-centred output to the fine node centres (clamped at the
-    border), rho = 1 + 3 U^2 o0, u = U (o1, o2); solid nodes rho = 1, u = 0;
-    then per case the fluid mean of rho - 1 is removed and, with it removed,
-    the staggered momenta: u_x -= (-1)^i sum((-1)^i rho u_x) / sum(rho) over
-    the fluid (likewise u_y with (-1)^j); these two sums change sign every
-    step of a bounce-back lattice and must start at zero."""
+    border, along x with nx and along y with ny), rho = 1 + 3 U^2 o0,
+    u = U (o1, o2); solid nodes rho = 1, u = 0.  For a cavity, the fluid
+    mean of rho - 1 is then removed and, with it removed, the staggered
+    momenta: u_x -= (-1)^i sum((-1)^i rho u_x) / sum(rho) over the fluid
+    (likewise u_y with (-1)^j); these two sums change sign every step of a
+    bounce-back lattice and must start at zero.  A channel keeps the
+    interpolated prediction."""
     out = np.asarray(out, np.float64)
     solid = np.asarray(solid, bool)
     n, res = out.shape[0], out.shape[1]
-    fine = solid.shape[1]
-    c = np.clip((np.arange(fine) + 0.5) * res / fine - 0.5, 0, res - 1)
-    i0 = np.minimum(c.astype(int), max(res - 2, 0))
-    i1 = np.minimum(i0 + 1, res - 1)
-    f = c - i0
-    rho = np.empty((n, fine, fine))
+    ny, nx = solid.shape[1], solid.shape[2]
+    kinds = _kinds(case_params)
+
+    def axis(fine):
+        c = np.clip((np.arange(fine) + 0.5) * res / fine - 0.5, 0, res - 1)
+        i0 = np.minimum(c.astype(int), max(res - 2, 0))
+        return i0, np.minimum(i0 + 1, res - 1), c - i0
+    x0, x1, fx = axis(nx)
+    y0, y1, fy = axis(ny)
+    rho = np.empty((n, ny, nx))
     ux, uy = np.empty_like(rho), np.empty_like(rho)
     for k in range(n):
         U = float(case_params[k][2])
         o = out[k]
-        rows0, rows1 = o[i0], o[i1]                 # interpolate along y (rows)
-        ry = (1 - f)[:, None, None] * rows0 + f[:, None, None] * rows1
-        v = (1 - f)[None, :, None] * ry[:, i0] + f[None, :, None] * ry[:, i1]
+        ry = (1 - fy)[:, None, None] * o[y0] + fy[:, None, None] * o[y1]   # along y (rows)
+        v = (1 - fx)[None, :, None] * ry[:, x0] + fx[None, :, None] * ry[:, x1]
         r = 1 + 3 * U * U * v[..., 0]
         a, b = U * v[..., 1], U * v[..., 2]
         s = solid[k]
         r[s], a[s], b[s] = 1.0, 0.0, 0.0
-        r[~s] -= (r[~s] - 1).mean()
-        sx = np.where(np.arange(fine) % 2 == 0, 1.0, -1.0)[None, :]
-        sy = np.where(np.arange(fine) % 2 == 0, 1.0, -1.0)[:, None]
-        R = r[~s].sum()
-        cx = (sx * r * a)[~s].sum() / R
-        cy = (sy * r * b)[~s].sum() / R
-        a = np.where(s, 0.0, a - sx * cx)
-        b = np.where(s, 0.0, b - sy * cy)
+        if kinds[k] == KIND_CAVITY:
+            r[~s] -= (r[~s] - 1).mean()
+            sx = np.where(np.arange(nx) % 2 == 0, 1.0, -1.0)[None, :]
+            sy = np.where(np.arange(ny) % 2 == 0, 1.0, -1.0)[:, None]
+            R = r[~s].sum()
+            cx = (sx * r * a)[~s].sum() / R
+            cy = (sy * r * b)[~s].sum() / R
+            a = np.where(s, 0.0, a - sx * cx)
+            b = np.where(s, 0.0, b - sy * cy)
         rho[k], ux[k], uy[k] = r, a, b
     return rho, ux, uy

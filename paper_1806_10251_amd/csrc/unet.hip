@@ -781,29 +781,36 @@ __device__ __forceinline__ void cell_range(int I, int fine, int res, int& a, int
   if (b <= a) b = a + 1;
 }
 
-__global__ void make_input_kernel(const uint8_t* solid, int fine, const float* cp, int n, int res,
-                                  bf16* x0) {
+// The case kind (case_params[cps c + 3] when cps == 4, else a cavity)
+// places the driven-boundary marker: the lid row (top) of a cavity, the
+// inlet column (left) of a channel.
+__device__ __forceinline__ int case_kind(const float* cp, int cps, long long c) {
+  return cps > 3 ? int(cp[cps * c + 3]) : UNET_KIND_CAVITY;
+}
+
+__global__ void make_input_kernel(const uint8_t* solid, int nx, int ny, const float* cp, int cps,
+                                  int n, int res, bf16* x0) {
   const long long total = (long long)n * res * res;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
        e += (long long)gridDim.x * blockDim.x) {
     const int i = int(e % res), j = int((e / res) % res);
     const long long c = e / ((long long)res * res);
     int i0, i1, j0, j1;
-    cell_range(i, fine, res, i0, i1);
-    cell_range(j, fine, res, j0, j1);
+    cell_range(i, nx, res, i0, i1);
+    cell_range(j, ny, res, j0, j1);
     int cnt = 0;
     for (int b = j0; b < j1; ++b)
-      for (int a = i0; a < i1; ++a) cnt += solid[(c * fine + b) * fine + a] != 0;
+      for (int a = i0; a < i1; ++a) cnt += solid[(c * ny + b) * nx + a] != 0;
     float v[UNET_IN_CHANNELS];
 #pragma unroll
     for (int k = 0; k < UNET_IN_CHANNELS; ++k) v[k] = 0.f;
     v[0] = float(cnt) / float((i1 - i0) * (j1 - j0));
-    v[1] = cp[3 * c + 0] / 500.f;
-    v[2] = cp[3 * c + 1];
-    v[3] = cp[3 * c + 2] / 0.1f;
+    v[1] = cp[cps * c + 0] / 500.f;
+    v[2] = cp[cps * c + 1];
+    v[3] = cp[cps * c + 2] / 0.1f;
     v[4] = (i + 0.5f) / res;
     v[5] = (j + 0.5f) / res;
-    v[6] = j == res - 1 ? 1.f : 0.f;
+    v[6] = (case_kind(cp, cps, c) == UNET_KIND_CHANNEL ? i == 0 : j == res - 1) ? 1.f : 0.f;
     v[7] = 1.f;
 #pragma unroll
     for (int q = 0; q < UNET_IN_CHANNELS / 8; ++q) {
@@ -829,21 +836,22 @@ __device__ float bilinear(const float* out, int ldo, long long c, int res, int c
 }
 
 __global__ void fields_kernel(const float* out, int ldo, int n, int res, const float* cp,
-                              const uint8_t* solid, int fine, float* rho, float* ux, float* uy) {
-  const long long total = (long long)n * fine * fine;
-  const float sc = float(res) / float(fine);
+                              int cps, const uint8_t* solid, int nx, int ny, float* rho,
+                              float* ux, float* uy) {
+  const long long total = (long long)n * nx * ny;
+  const float scx = float(res) / float(nx), scy = float(res) / float(ny);
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
        e += (long long)gridDim.x * blockDim.x) {
-    const int i = int(e % fine), j = int((e / fine) % fine);
-    const long long c = e / ((long long)fine * fine);
+    const int i = int(e % nx), j = int((e / nx) % ny);
+    const long long c = e / ((long long)nx * ny);
     if (solid[e]) {
       rho[e] = 1.f;
       ux[e] = 0.f;
       uy[e] = 0.f;
       continue;
     }
-    const float U = cp[3 * c + 2];
-    const float u = (i + 0.5f) * sc - 0.5f, v = (j + 0.5f) * sc - 0.5f;
+    const float U = cp[cps * c + 2];
+    const float u = (i + 0.5f) * scx - 0.5f, v = (j + 0.5f) * scy - 0.5f;
     rho[e] = 1.f + 3.f * U * U * bilinear(out, ldo, c, res, 0, u, v);
     ux[e] = U * bilinear(out, ldo, c, res, 1, u, v);
     uy[e] = U * bilinear(out, ldo, c, res, 2, u, v);
@@ -858,12 +866,16 @@ __global__ void fields_kernel(const float* out, int ldo, int n, int res, const f
 // with e_x != 0 to a column of the other parity, or reverse it in place), so
 // a start with Ix or Iy != 0 never settles: the state keeps an undamped
 // period-2 oscillation.  u_x -= (-1)^i Ix / sum rho (likewise u_y) makes
-// both zero, as they are for the state at rest.
+// both zero, as they are for the state at rest.  Closed lattices (cavities)
+// only: a channel's inlet and outlet change its mass and do not keep these
+// sums, so its prediction is left as it is.
 __global__ __launch_bounds__(256) void mass_fix_kernel(float* rho, float* ux, float* uy,
-                                                       const uint8_t* solid, int fine) {
+                                                       const uint8_t* solid, int nx, int ny,
+                                                       const float* cp, int cps) {
   __shared__ double s[4][256];
-  const long long base = (long long)blockIdx.x * fine * fine;
-  const long long cnt = (long long)fine * fine;
+  if (case_kind(cp, cps, blockIdx.x) != UNET_KIND_CAVITY) return;
+  const long long base = (long long)blockIdx.x * nx * ny;
+  const long long cnt = (long long)nx * ny;
   auto block_sum = [&](int q) {
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
@@ -887,7 +899,7 @@ __global__ __launch_bounds__(256) void mass_fix_kernel(float* rho, float* ux, fl
     if (!solid[base + k]) {
       const float r = rho[base + k] - mean;
       rho[base + k] = r;
-      const int i = int(k % fine), j = int(k / fine);
+      const int i = int(k % nx), j = int(k / nx);
       sx += (i & 1 ? -1.0 : 1.0) * (double)r * (double)ux[base + k];
       sy += (j & 1 ? -1.0 : 1.0) * (double)r * (double)uy[base + k];
       sr += (double)r;
@@ -900,13 +912,41 @@ __global__ __launch_bounds__(256) void mass_fix_kernel(float* rho, float* ux, fl
   const float mx = R > 0 ? float(Ix / R) : 0.f, my = R > 0 ? float(Iy / R) : 0.f;
   for (long long k = threadIdx.x; k < cnt; k += 256)
     if (!solid[base + k]) {
-      const int i = int(k % fine), j = int(k / fine);
+      const int i = int(k % nx), j = int(k / nx);
       ux[base + k] -= (i & 1) ? -mx : mx;
       uy[base + k] -= (j & 1) ? -my : my;
     }
 }
 
 }  // namespace
+
+// ===========================================================================
+// Input and output maps of either shape (cps: floats per case in case_params)
+// ===========================================================================
+static int launch_make_input(const uint8_t* solid, int nx, int ny, const float* cp, int cps, int n,
+                      int res, void* x0, void* stream) {
+  if (!solid || !cp || !x0 || n <= 0 || res <= 0 || nx <= 0 || ny <= 0)
+    return fail(UNET_EINVAL, "make_input: bad arguments");
+  hipLaunchKernelGGL(make_input_kernel, dim3(grid_for((long long)n * res * res)), dim3(256), 0,
+                     as_stream(stream), solid, nx, ny, cp, cps, n, res, static_cast<bf16*>(x0));
+  UCHECK(hipGetLastError());
+  return UNET_OK;
+}
+
+static int launch_fields(const float* out, int ldo, int n, int res, const float* cp, int cps,
+                  const uint8_t* solid, int nx, int ny, float* rho, float* ux, float* uy,
+                  void* stream) {
+  if (!out || !cp || !solid || !rho || !ux || !uy || n <= 0 || res < 2 || nx <= 0 || ny <= 0 ||
+      ldo < 3)
+    return fail(UNET_EINVAL, "fields_from_output: bad arguments");
+  hipStream_t st = as_stream(stream);
+  hipLaunchKernelGGL(fields_kernel, dim3(grid_for((long long)n * nx * ny)), dim3(256), 0, st,
+                     out, ldo, n, res, cp, cps, solid, nx, ny, rho, ux, uy);
+  hipLaunchKernelGGL(mass_fix_kernel, dim3(n), dim3(256), 0, st, rho, ux, uy, solid, nx, ny, cp,
+                     cps);
+  UCHECK(hipGetLastError());
+  return UNET_OK;
+}
 
 // ===========================================================================
 // C ABI: layers
@@ -1103,26 +1143,24 @@ int unet_adam(float* p, float* m, float* v, const float* g, void* pb, int64_t co
 
 int unet_make_input(const uint8_t* solid, int32_t fine, const float* case_params, int32_t n,
                     int32_t res, void* x0, void* stream) {
-  if (!solid || !case_params || !x0 || n <= 0 || res <= 0 || fine <= 0)
-    return fail(UNET_EINVAL, "make_input: bad arguments");
-  hipLaunchKernelGGL(make_input_kernel, dim3(grid_for((long long)n * res * res)), dim3(256), 0,
-                     as_stream(stream), solid, fine, case_params, n, res, static_cast<bf16*>(x0));
-  UCHECK(hipGetLastError());
-  return UNET_OK;
+  return launch_make_input(solid, fine, fine, case_params, 3, n, res, x0, stream);
 }
 
 int unet_fields_from_output(const float* out, int32_t ldo, int32_t n, int32_t res,
                             const float* case_params, const uint8_t* solid, int32_t fine,
                             float* rho, float* ux, float* uy, void* stream) {
-  if (!out || !case_params || !solid || !rho || !ux || !uy || n <= 0 || res < 2 || fine <= 0 ||
-      ldo < 3)
-    return fail(UNET_EINVAL, "fields_from_output: bad arguments");
-  hipStream_t st = as_stream(stream);
-  hipLaunchKernelGGL(fields_kernel, dim3(grid_for((long long)n * fine * fine)), dim3(256), 0, st,
-                     out, ldo, n, res, case_params, solid, fine, rho, ux, uy);
-  hipLaunchKernelGGL(mass_fix_kernel, dim3(n), dim3(256), 0, st, rho, ux, uy, solid, fine);
-  UCHECK(hipGetLastError());
-  return UNET_OK;
+  return launch_fields(out, ldo, n, res, case_params, 3, solid, fine, fine, rho, ux, uy, stream);
+}
+
+int unet_make_input_rect(const uint8_t* solid, int32_t nx, int32_t ny, const float* case_params,
+                         int32_t n, int32_t res, void* x0, void* stream) {
+  return launch_make_input(solid, nx, ny, case_params, 4, n, res, x0, stream);
+}
+
+int unet_fields_from_output_rect(const float* out, int32_t ldo, int32_t n, int32_t res,
+                                 const float* case_params, const uint8_t* solid, int32_t nx,
+                                 int32_t ny, float* rho, float* ux, float* uy, void* stream) {
+  return launch_fields(out, ldo, n, res, case_params, 4, solid, nx, ny, rho, ux, uy, stream);
 }
 
 }  // extern "C"

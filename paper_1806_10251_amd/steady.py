@@ -148,7 +148,7 @@ def batch_arm(cases, tol, max_steps, storage="f64", choice=None, warm_net=None, 
         # the cold start is the fallback: a warm-started case that diverges
         # runs again from rest (same filter); its steps and the time of the
         # second run are added to the arm
-        redo = [i for i, k in enumerate(cases) if surrogate.covers(k) and st[i] == 3]
+        redo = [i for i, k in enumerate(cases) if surrogate.covers(k, warm_net) and st[i] == 3]
         if redo:
             if log:
                 log(f"[tts] {len(redo)} warm-started case(s) diverged; rerun from rest")

@@ -39,8 +39,10 @@ from . import steady
 from . import unet as U
 
 RES = 128
-DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights",
-                               "unet_cavity128.npy")
+WEIGHTS_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights")
+CAVITY_WEIGHTS = os.path.join(WEIGHTS_DIR, "unet_cavity128.npy")
+MIX_WEIGHTS = os.path.join(WEIGHTS_DIR, "unet_mix128.npy")
+DEFAULT_WEIGHTS = MIX_WEIGHTS if os.path.exists(MIX_WEIGHTS) else CAVITY_WEIGHTS
 
 
 def cavity_cases(n, seed, side, re_lo=50.0, re_hi=500.0):
@@ -52,12 +54,19 @@ def cavity_cases(n, seed, side, re_lo=50.0, re_hi=500.0):
                       channel_frac=0.0)
 
 
+def channel_cases(n, seed, side, re_lo=50.0, re_hi=500.0):
+    """Seeded channels 4 side x side (parabolic inlet, convective outlet)
+    with 1-4 rectangular obstacles, otherwise drawn as cavity_cases."""
+    from workloads import draw_cases
+    return draw_cases(n, seed, side_lo=side, side_hi=side, re_lo=re_lo, re_hi=re_hi,
+                      channel_frac=1.0)
+
+
 def case_params(cases):
-    return np.array([[k.re, k.gamma, k.u_ref] for k in cases], np.float32)
-
-
-def _lat_kw(k):
-    return dict(nu=k.nu, gamma=k.gamma, u_lid=k.u_ref)
+    """Network case parameters (Re, gamma, U, kind) per case."""
+    return np.array([[k.re, k.gamma, k.u_ref,
+                      U.KIND_CHANNEL if k.kind == "channel" else U.KIND_CAVITY] for k in cases],
+                    np.float32)
 
 
 def steady_fields(cases, tol=1e-8, max_steps=400000, chunk=512, init=None, filter_at=(),
@@ -78,7 +87,8 @@ def steady_fields(cases, tol=1e-8, max_steps=400000, chunk=512, init=None, filte
     for i0 in range(0, n, chunk):
         part = cases[i0:i0 + chunk]
         grids = [L.make_grid(k.nx, k.ny, k.sides) for k in part]
-        params = [L.make_params(storage="f64", check_every=100, **_lat_kw(k)) for k in part]
+        params = [L.make_params(storage="f64", check_every=100, **steady.case_kw(k))
+                  for k in part]
         b = L.Batch(grids, [k.mask for k in part], params)
         import torch
         torch.cuda.synchronize()
@@ -106,27 +116,63 @@ def steady_fields(cases, tol=1e-8, max_steps=400000, chunk=512, init=None, filte
     return rho, ux, uy, steps, status, secs
 
 
-def targets(cases, rho, ux, uy):
+def targets(cases, rho, ux, uy, res=None):
+    """Training targets (rho - 1) / (3 U^2), u / U per fluid node and the
+    fluid mask.  With res given and lattices of another size, both are taken
+    to the network's res x res cells (the cells of the input map): the mean
+    over the fluid nodes of a cell, which is fluid if it holds any."""
     cp = case_params(cases).astype(np.float64)
     Uv = cp[:, 2][:, None, None]
     t = np.stack([(rho - 1.0) / (3.0 * Uv ** 2), ux / Uv, uy / Uv], axis=-1)
+    # Channels: velocity only.  Their pressure drop, (rho - 1) / (3 U^2) of
+    # order 100 / Re times the blockage, is one to two orders of magnitude
+    # above a cavity's pressure variations in these units and dominated the
+    # loss (a first training run on both kinds stayed at a loss of about 150);
+    # with a zero target the network returns rho ~ 1 for a channel.
+    is_channel = np.array([k.kind == "channel" for k in cases])
+    t[is_channel, ..., 0] = 0.0
     fluid = np.stack([(k.mask == 0) for k in cases]).astype(np.uint8)
     t = np.where(fluid[..., None] == 1, t, 0.0)
+    n, ny, nx = fluid.shape
+    if res is not None and (ny, nx) != (res, res):
+        def cells(fine):
+            lo = [I * fine // res for I in range(res)]
+            return lo, [max((I + 1) * fine // res, lo[I] + 1) for I in range(res)]
+        (lx, hx), (ly, hy) = cells(nx), cells(ny)
+        tc = np.zeros((n, res, res, 3))
+        fc = np.zeros((n, res, res), np.uint8)
+        for J in range(res):
+            for I in range(res):
+                f = fluid[:, ly[J]:hy[J], lx[I]:hx[I]].reshape(n, -1).astype(np.float64)
+                v = t[:, ly[J]:hy[J], lx[I]:hx[I]].reshape(n, -1, 3)
+                cnt = f.sum(1)
+                tc[:, J, I] = (v * f[..., None]).sum(1) / np.maximum(cnt, 1)[:, None]
+                fc[:, J, I] = cnt > 0
+        t, fluid = tc, fc
     return t.astype(np.float32), fluid
 
 
 class Dataset:
-    """Network inputs and targets resident on the device."""
+    """Network inputs and targets resident on the device.  groups: one or
+    more (cases, rho, ux, uy) of one lattice shape each."""
 
-    def __init__(self, cases, rho, ux, uy):
+    def __init__(self, *groups):
         import torch
-        t, fluid = targets(cases, rho, ux, uy)
-        solid = torch.tensor(np.stack([k.mask for k in cases]).astype(np.uint8), device="cuda")
-        cp = torch.tensor(case_params(cases), device="cuda")
-        self.x0 = U.make_input(solid, cp, RES)
-        self.t = torch.tensor(t, device="cuda")
-        self.fluid = torch.tensor(fluid, device="cuda")
-        self.n = len(cases)
+        if len(groups) == 4 and not isinstance(groups[0], tuple):
+            groups = (tuple(groups),)
+        xs, ts, fs = [], [], []
+        for cases, rho, ux, uy in groups:
+            t, fluid = targets(cases, rho, ux, uy, RES)
+            solid = torch.tensor(np.stack([k.mask for k in cases]).astype(np.uint8),
+                                 device="cuda")
+            cp = torch.tensor(case_params(cases), device="cuda")
+            xs.append(U.make_input(solid, cp, RES))
+            ts.append(torch.tensor(t, device="cuda"))
+            fs.append(torch.tensor(fluid, device="cuda"))
+        self.x0 = torch.cat(xs)
+        self.t = torch.cat(ts)
+        self.fluid = torch.cat(fs)
+        self.n = int(self.x0.shape[0])
 
 
 def train(net, data, epochs, batch, lr=1e-3, lr_end=1e-4, seed=0, log=None):
@@ -165,22 +211,25 @@ def evaluate_loss(net, data, batch):
     return float(np.sum(losses) / data.n)
 
 
-def covers(case):
-    """True for the cases the network predicts (square cavities)."""
-    return case.kind == "cavity" and case.nx == case.ny
+def covers(case, net=None):
+    """True for the cases the network predicts: the kinds its weights were
+    trained on (net.kinds, set by load_into; square cavities when unknown)."""
+    kinds = getattr(net, "kinds", ("cavity",)) if net is not None else ("cavity",)
+    if case.kind == "cavity":
+        return "cavity" in kinds and case.nx == case.ny
+    return case.kind in kinds
 
 
 def predict_fields(net, cases):
     """Predicted (rho, ux, uy) device tensors [ny][nx] per case; None for
-    cases that are not square cavities (the network was trained on those;
-    such cases keep the cold start).  Cases of one size share a forward
-    pass."""
+    cases the network does not cover (covers(); they keep the cold start).
+    Cases of one shape share a forward pass."""
     import torch
     out = [None] * len(cases)
     by_size = {}
     for i, k in enumerate(cases):
-        if covers(k):
-            by_size.setdefault(k.nx, []).append(i)
+        if covers(k, net):
+            by_size.setdefault((k.ny, k.nx), []).append(i)
     for fine, idx in by_size.items():
         group = [cases[i] for i in idx]
         solid = torch.tensor(np.stack([k.mask for k in group]).astype(np.uint8), device="cuda")
@@ -256,12 +305,28 @@ def bench_train(steps=50, batch=16, seed=0):
     return ms, network_flops(RES, batch)[1] / (ms * 1e-3) / 1e12
 
 
-def save(net, path):
+def _kinds_path(path):
+    return os.path.splitext(path)[0] + ".kinds.json"
+
+
+def save(net, path, kinds=("cavity",)):
+    """Parameters (.npy) and the case kinds they were trained on (.kinds.json)."""
+    import json
     np.save(path, net.params())
+    with open(_kinds_path(path), "w") as f:
+        json.dump({"kinds": list(kinds)}, f)
 
 
 def load_into(net, path):
+    """Load parameters and record on `net` the kinds they cover (square
+    cavities when the file has no kinds record)."""
+    import json
     net.set_params(np.load(path, allow_pickle=False))
+    try:
+        with open(_kinds_path(path)) as f:
+            net.kinds = tuple(json.load(f)["kinds"])
+    except OSError:
+        net.kinds = ("cavity",)
 
 
 def _log(msg):
@@ -314,7 +379,7 @@ def evaluate(net, cases, tols=(1e-8, 1e-9, 1e-10), max_steps=600000, segment=200
         sec = time.perf_counter() - t0
         fields = [b.fields(i, k.ny, k.nx)[1:] for i, k in enumerate(cases)]
         b.close()
-        redo = [i for i in range(n) if warm and status[i] == 3]
+        redo = [i for i in range(n) if warm and covers(cases[i], net) and status[i] == 3]
         if redo:
             # the cold start is the fallback for a warm start that diverges
             sec2, total2, status2, fields2 = arm(name + " (cold fallback)", tol, False, filter_at,
@@ -355,6 +420,9 @@ def main(argv=None):
     t.add_argument("--batch", type=int, default=16)
     t.add_argument("--lr", type=float, default=1e-3)
     t.add_argument("--max-steps", type=int, default=300000)
+    t.add_argument("--channels", type=int, default=0,
+                   help="also train on this many channels 4*128 x 128 (seed + 1)")
+    t.add_argument("--channel-max-steps", type=int, default=60000)
     t.add_argument("--out", required=True)
     t.add_argument("--data-cache", default="")
     bt = sub.add_parser("bench-train")
@@ -364,8 +432,7 @@ def main(argv=None):
     ev.add_argument("--cases", type=int, default=64)
     ev.add_argument("--side", type=int, default=512)
     ev.add_argument("--seed", type=int, default=5151)
-    ev.add_argument("--weights", default=os.path.join(os.path.dirname(__file__), "weights",
-                                                      "unet_cavity128.npy"))
+    ev.add_argument("--weights", default=DEFAULT_WEIGHTS)
     ev.add_argument("--tols", default="1e-8,1e-9,1e-10")
     ev.add_argument("--max-steps", type=int, default=600000)
     args = ap.parse_args(argv)
@@ -411,14 +478,27 @@ def main(argv=None):
             np.savez(args.data_cache, rho=rho, ux=ux, uy=uy, status=status)
     keep = [i for i in range(len(cases)) if status[i] == 1]
     cases = [cases[i] for i in keep]
-    data = Dataset(cases, rho[keep], ux[keep], uy[keep])
+    groups = [(cases, rho[keep], ux[keep], uy[keep])]
+    kinds = ["cavity"]
+    if args.channels:
+        ch = channel_cases(args.channels, args.seed + 1, RES)
+        rho, ux, uy, steps, status, sec = steady_fields(ch, max_steps=args.channel_max_steps,
+                                                        log=_log)
+        _log(f"generated {len(ch)} steady channel fields in {sec:.1f} s; converged "
+             f"{(status == 1).sum()}, steps median {int(np.median(steps))}")
+        keep = [i for i in range(len(ch)) if status[i] == 1]
+        groups.append(([ch[i] for i in keep], rho[keep], ux[keep], uy[keep]))
+        kinds.append("channel")
+        del rho, ux, uy
+    data = Dataset(*groups)
+    _log(f"training set: {data.n} cases")
     net = U.UNet(max_batch=args.batch, res=RES, seed=args.seed)
     t0 = time.perf_counter()
     hist = train(net, data, args.epochs, args.batch, lr=args.lr, seed=args.seed, log=_log)
     torch.cuda.synchronize()
     _log(f"trained {len(hist)} steps in {time.perf_counter() - t0:.1f} s; "
          f"final loss {np.mean(hist[-20:]):.4e}")
-    save(net, args.out)
+    save(net, args.out, kinds)
 
 
 if __name__ == "__main__":

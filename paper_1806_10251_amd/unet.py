@@ -46,6 +46,8 @@ def load():
         "unet_adam": [vp, vp, vp, vp, vp, i64, dbl, dbl, dbl, dbl, i64, vp],
         "unet_make_input": [vp, i32, vp, i32, i32, vp, vp],
         "unet_fields_from_output": [vp, i32, i32, i32, vp, vp, i32, vp, vp, vp, vp],
+        "unet_make_input_rect": [vp, i32, i32, vp, i32, i32, vp, vp],
+        "unet_fields_from_output_rect": [vp, i32, i32, i32, vp, vp, i32, i32, vp, vp, vp, vp],
         "unet_create": [i32, i32, u64, P(vp)],
         "unet_destroy": [vp],
         "unet_set_stream": [vp, vp],
@@ -182,25 +184,43 @@ def adam(p, m, v, g, t, lr, beta1=0.9, beta2=0.999, eps=1e-8, pb=None):
                             int(t), _stream()))
 
 
+KIND_CAVITY, KIND_CHANNEL = 0, 1
+
+
 def make_input(solid, case_params, res):
-    """solid u8 [n,fine,fine]; case_params f32 [n,3] = (Re, gamma, U)."""
+    """solid u8 [n,ny,nx]; case_params f32 [n,3] = (Re, gamma, U) for square
+    cavities, or [n,4] = (Re, gamma, U, kind) for any shape and kind."""
     import torch
-    n, fine, _ = solid.shape
+    n, ny, nx = solid.shape
     x0 = torch.empty((n, res, res, IN_CHANNELS), device=solid.device, dtype=torch.bfloat16)
-    _check(load().unet_make_input(_p(solid), fine, _p(case_params), n, res, _p(x0), _stream()))
+    if case_params.shape[1] == 4:
+        _check(load().unet_make_input_rect(_p(solid), nx, ny, _p(case_params), n, res, _p(x0),
+                                           _stream()))
+    else:
+        if nx != ny:
+            raise ValueError("three case parameters describe square cavities only")
+        _check(load().unet_make_input(_p(solid), nx, _p(case_params), n, res, _p(x0), _stream()))
     return x0
 
 
 def fields_from_output(out, case_params, solid):
-    """out f32 [n,res,res,ldo]; solid u8 [n,fine,fine] -> rho, ux, uy f32 [n,fine,fine]."""
+    """out f32 [n,res,res,ldo]; solid u8 [n,ny,nx]; case_params as for
+    make_input -> rho, ux, uy f32 [n,ny,nx]."""
     import torch
     n, res, _, ldo = out.shape
-    fine = solid.shape[1]
-    rho = torch.empty((n, fine, fine), device=out.device, dtype=torch.float32)
+    ny, nx = solid.shape[1], solid.shape[2]
+    rho = torch.empty((n, ny, nx), device=out.device, dtype=torch.float32)
     ux = torch.empty_like(rho)
     uy = torch.empty_like(rho)
-    _check(load().unet_fields_from_output(_p(out), ldo, n, res, _p(case_params), _p(solid), fine,
-                                          _p(rho), _p(ux), _p(uy), _stream()))
+    if case_params.shape[1] == 4:
+        _check(load().unet_fields_from_output_rect(_p(out), ldo, n, res, _p(case_params),
+                                                   _p(solid), nx, ny, _p(rho), _p(ux), _p(uy),
+                                                   _stream()))
+    else:
+        if nx != ny:
+            raise ValueError("three case parameters describe square cavities only")
+        _check(load().unet_fields_from_output(_p(out), ldo, n, res, _p(case_params), _p(solid),
+                                              nx, _p(rho), _p(ux), _p(uy), _stream()))
     return rho, ux, uy
 
 

@@ -198,6 +198,39 @@ def test_input_and_output_maps(U):
     np.testing.assert_allclose(host(uy), vr, rtol=0, atol=1e-6)
 
 
+def test_rect_input_and_output_maps(U):
+    """The maps for lattices of any shape and kind: channels (4:1, inlet
+    marker on the left column, no mass or staggered-momentum correction)
+    against the reference, and a square cavity given as kind 0 equal to the
+    three-parameter maps."""
+    import torch
+    rng = np.random.default_rng(16)
+    solid = (rng.random((2, 20, 80)) > 0.85).astype(np.uint8)
+    cp = np.array([[100.0, 0.3, 0.02, 1.0], [450.0, 1.0, 0.05, 1.0]], np.float32)
+    for res in (16, 24):
+        x0 = host(U.make_input(dev(solid, torch.uint8), dev(cp, torch.float32), res))
+        np.testing.assert_allclose(x0, R.bf16(R.make_input(solid, cp.astype(np.float64), res)),
+                                   rtol=2 ** -8, atol=0)
+    out = rng.standard_normal((2, 16, 16, 32)).astype(np.float32).astype(np.float64)
+    rho, ux, uy = U.fields_from_output(dev(out, torch.float32), dev(cp, torch.float32),
+                                       dev(solid, torch.uint8))
+    rr, ur, vr = R.fields_from_output(out, cp.astype(np.float64), solid)
+    np.testing.assert_allclose(host(rho), rr, rtol=0, atol=2e-6)
+    np.testing.assert_allclose(host(ux), ur, rtol=0, atol=1e-6)
+    np.testing.assert_allclose(host(uy), vr, rtol=0, atol=1e-6)
+    # a square cavity: kind 0 with four parameters equals the three-parameter maps
+    sq = (rng.random((2, 32, 32)) > 0.8).astype(np.uint8)
+    cp3 = np.array([[100.0, 0.3, 0.05], [450.0, 1.0, 0.1]], np.float32)
+    cp4 = np.concatenate([cp3, np.zeros((2, 1), np.float32)], axis=1)
+    a = U.make_input(dev(sq, torch.uint8), dev(cp3, torch.float32), 24)
+    b = U.make_input(dev(sq, torch.uint8), dev(cp4, torch.float32), 24)
+    assert torch.equal(a, b)
+    f3 = U.fields_from_output(dev(out, torch.float32), dev(cp3, torch.float32), dev(sq, torch.uint8))
+    f4 = U.fields_from_output(dev(out, torch.float32), dev(cp4, torch.float32), dev(sq, torch.uint8))
+    for p3, p4 in zip(f3, f4):
+        assert torch.equal(p3, p4)
+
+
 def _net_inputs(res, n, seed):
     rng = np.random.default_rng(seed)
     solid = np.zeros((n, res, res), np.uint8)

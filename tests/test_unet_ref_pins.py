@@ -132,3 +132,37 @@ def test_make_input_fraction_on_uneven_grids():
     y = U.make_input(solid, [[100.0, 0.5, 0.1]], 40)
     assert set(np.unique(y[0, :, :, 0])) <= {0.0, 1.0}
     np.testing.assert_allclose(y[0, ::2, ::2, 0], solid[0])
+
+
+def test_channel_input_marks_the_inlet_and_keeps_the_solid_area():
+    """A 4:1 channel maps onto the square input with four fine columns per
+    coarse cell: the solid fraction keeps the solid area, and channel 6
+    marks the inlet column (left), not the top row."""
+    rng = np.random.default_rng(8)
+    solid = (rng.random((1, 16, 64)) > 0.7).astype(np.uint8)
+    x = U.make_input(solid, [[100.0, 0.5, 0.03, U.KIND_CHANNEL]], 16)
+    np.testing.assert_allclose(x[0, :, :, 0].mean(), solid.mean())
+    np.testing.assert_allclose(x[0, 2, 3, 0], solid[0, 2, 12:16].mean())
+    assert np.all(x[0, :, 0, 6] == 1.0) and np.all(x[0, :, 1:, 6] == 0.0)
+    c = U.make_input(solid[:, :, :16], [[100.0, 0.5, 0.03, U.KIND_CAVITY]], 16)
+    assert np.all(c[0, 15, :, 6] == 1.0) and np.all(c[0, :15, :, 6] == 0.0)
+
+
+def test_channel_fields_keep_the_prediction():
+    """Uniform output (0, 1, 0): a channel gets rho = 1 and u = (U, 0) at
+    every fluid node (interpolating a constant, no correction); a cavity of
+    the same output gets its staggered x-momentum removed (a uniform u_x
+    has a nonzero staggered sum on an odd number of fluid columns)."""
+    out = np.zeros((1, 8, 8, 3))
+    out[..., 1] = 1.0
+    solid = np.zeros((1, 6, 24), bool)
+    solid[0, 2:4, 10:13] = True
+    r, a, b = U.fields_from_output(out, [[100.0, 0.5, 0.04, U.KIND_CHANNEL]], solid)
+    fl = ~solid[0]
+    assert np.all(r[0][fl] == 1.0) and np.allclose(a[0][fl], 0.04) and np.all(b[0] == 0.0)
+    assert np.all(a[0][solid[0]] == 0.0)
+    sq = np.zeros((1, 9, 9), bool)
+    r, a, b = U.fields_from_output(out, [[100.0, 0.5, 0.04, U.KIND_CAVITY]], sq)
+    sx = np.where(np.arange(9) % 2 == 0, 1.0, -1.0)[None, :]
+    assert abs((sx * r[0] * a[0]).sum()) < 1e-15
+    assert not np.allclose(a[0], 0.04)
