@@ -6,22 +6,24 @@ from the lattice Boltzmann library itself (batched FP64 runs to residual
 library's BF16 MFMA kernels; the predicted (rho, u) initialise the lattice
 at their equilibrium, so the iteration and its fixed point are unchanged and
 only the starting point moves.  The cold start (rest state) remains the
-fallback for every case the network does not cover (anything but a square
-cavity) and for a warm-started case that diverges (it runs again from rest).
+fallback for every case the network does not cover (the kinds its weights
+were trained on: square cavities and channels for the default weights) and
+for a warm-started case that diverges (it runs again from rest).
 
-Targets (per fluid node): (rho - 1) / (3 U^2), u_x / U, u_y / U.  The
-network works at a fixed resolution (128 x 128); a larger lattice is
-described to it by the solid fraction of each coarse cell, and its output is
-interpolated bilinearly to the lattice (unet_fields_from_output), with the
-fluid mean of rho - 1 removed so that a closed cavity keeps the cold start's
-mass and with the staggered momenta that bounce-back lattices never damp
-removed.  A warm-started state is also replaced, after its first step and
+Targets (per fluid node): (rho - 1) / (3 U^2), u_x / U, u_y / U (a
+channel's density target is zero: velocity only).  The network works at a
+fixed resolution (128 x 128); a lattice of any shape is described to it by
+the solid fraction of each coarse cell, and its output is interpolated
+bilinearly to the lattice (unet_fields_from_output_rect), for a cavity with
+the fluid mean of rho - 1 removed so that the closed lattice keeps the cold
+start's mass and with the staggered momenta that bounce-back lattices never
+damp removed.  A warm-started state is also replaced, after its first step and
 after 1000 steps, by the mean of its last two steps (Batch.average_last_two):
 the prediction excites period-2 components that barely decay and would
 otherwise dominate the one-step residual.
 
 Command line (one GPU):
-  python -m paper_1806_10251_amd.surrogate train --out weights.npy
+  python -m paper_1806_10251_amd.surrogate train --channels 1500 --epochs 60 --out weights.npy
   python -m paper_1806_10251_amd.surrogate bench-train   (training-step timing)
 """
 from __future__ import annotations
