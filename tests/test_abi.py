@@ -37,6 +37,27 @@ def test_library_exports_every_declared_symbol(lib):
     assert not missing, missing
 
 
+def declared_unet_functions():
+    text = open(os.path.join(ROOT, "include", "unet.h")).read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(unet_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_network_symbol(lib):
+    """include/unet.h: every declared function is exported by the same
+    library and has a ctypes signature in the binding."""
+    from paper_1806_10251_amd import unet
+    lbm, _ = lib
+    raw = ctypes.CDLL(lbm.LIB_PATH)
+    names = declared_unet_functions()
+    assert "unet_make_input_rect" in names and "unet_train_step" in names
+    missing = [f for f in names if not hasattr(raw, f)]
+    assert not missing, missing
+    L = unet.load()
+    for f in names:
+        assert getattr(L, f).argtypes is not None, f
+
+
 def test_launch_shapes_are_listed(lib):
     lbm, _ = lib
     shapes = lbm.launch_shapes()
