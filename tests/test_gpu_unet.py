@@ -321,8 +321,9 @@ def test_held_out_cold_versus_warm_start(U):
     two-step filter: the learned warm start and the cold start reach the
     same steady state (against a run to residual 1e-11) within the accuracy
     the tolerance allows, and the steps of both arms are recorded.  The
-    network's share is small by design (its 15-20 % field error removes at
-    most ln(1/0.15) of the ln(1/1e-8) decades the cold start needs); the
+    network's share is small by design (its velocity error of about a
+    third, recorded here, removes at most ln(1/0.35) of the ln(1/1e-8)
+    decades the cold start needs); the
     test bounds it from below (the warm start must not cost more than 10 %
     extra steps) rather than asserting a gain."""
     import os
@@ -339,9 +340,11 @@ def test_held_out_cold_versus_warm_start(U):
     sc, stc, tc, fc = SD.batch_arm(cases, 1e-8, 300000, "f64", filter_at=S.WARM_FILTER)
     sw, stw, tw, fw = SD.batch_arm(cases, 1e-8, 300000, "f64", warm_net=net,
                                    filter_at=S.WARM_FILTER)
-    net.close()
     ok = [i for i in range(len(cases)) if st_ref[i] == 1]
+    pe = _prediction_error(S, net, cases, ref, ok)
+    net.close()
     ec, ew = SD.max_error(cases, fc, ref, ok), SD.max_error(cases, fw, ref, ok)
+    _say("prediction error", pe)
     _say("cold+filter steps", int(sc.sum()), "converged", int((stc == 1).sum()), "error", ec,
          f"{tc:.2f} s")
     _say("warm+filter steps", int(sw.sum()), "converged", int((stw == 1).sum()), "error", ew,
@@ -349,7 +352,59 @@ def test_held_out_cold_versus_warm_start(U):
     assert len(ok) == len(cases)
     assert (stc == 1).all() and (stw == 1).all()
     assert ec < 1e-3 and ew < 1e-3
+    assert pe < 0.5
     assert sw.sum() <= 1.1 * sc.sum()
+
+
+def _prediction_error(S, net, cases, ref, ok):
+    """Mean over the cases in ok of |u_pred - u_ref| / |u_ref| (L2 over the
+    fluid nodes, both velocity components)."""
+    pred = S.predict_fields(net, cases)
+    errs = []
+    for i in ok:
+        fl = cases[i].mask == 0
+        pu, pv = (t.float().cpu().numpy().astype(np.float64) for t in pred[i][1:])
+        ru, rv = ref[i]
+        num = np.sqrt(((pu - ru)[fl] ** 2 + (pv - rv)[fl] ** 2).sum())
+        errs.append(num / np.sqrt((ru[fl] ** 2 + rv[fl] ** 2).sum()))
+    return float(np.mean(errs))
+
+
+def test_held_out_channels_cold_versus_warm_start(U):
+    """Held-out channels 512 x 128 (seed outside the training set, obstacles,
+    Re 50-500), FP64, residual 1e-8, both arms with the same two-step
+    filter: the warm start reaches the same steady state as the cold start
+    (against a run to residual 1e-10), its steps are recorded next to the
+    cold start's, and the prediction's velocity error against the steady
+    field is recorded (bounded loosely: a wrong map of the 4:1 lattice onto
+    the square input would be off by order one)."""
+    import os
+    from paper_1806_10251_amd import steady as SD
+    from paper_1806_10251_amd import surrogate as S
+    if not os.path.exists(S.DEFAULT_WEIGHTS):
+        pytest.skip("no trained weights")
+    net = U.UNet(max_batch=16, res=S.RES, seed=0)
+    S.load_into(net, S.DEFAULT_WEIGHTS)
+    if "channel" not in net.kinds:
+        net.close()
+        pytest.skip("weights do not cover channels")
+    cases = S.channel_cases(8, 4343, S.RES)
+    _say("held-out cold vs warm: 8 channels 512x128, FP64, tol 1e-8")
+    _, st_ref, _, ref = SD.batch_arm(cases, 1e-10, 200000, "f64", filter_at=S.WARM_FILTER)
+    sc, stc, tc, fc = SD.batch_arm(cases, 1e-8, 100000, "f64", filter_at=S.WARM_FILTER)
+    sw, stw, tw, fw = SD.batch_arm(cases, 1e-8, 100000, "f64", warm_net=net,
+                                   filter_at=S.WARM_FILTER)
+    ok = [i for i in range(len(cases)) if st_ref[i] == 1 and stc[i] == 1 and stw[i] == 1]
+    pe = _prediction_error(S, net, cases, ref, ok)
+    net.close()
+    ec, ew = SD.max_error(cases, fc, ref, ok), SD.max_error(cases, fw, ref, ok)
+    _say("converged in all arms", len(ok), "of", len(cases), "prediction error", pe)
+    _say("cold+filter steps", int(sc[ok].sum()), "error", ec, f"{tc:.2f} s")
+    _say("warm+filter steps", int(sw[ok].sum()), "error", ew, f"{tw:.2f} s")
+    assert len(ok) >= 6
+    assert ec < 1e-3 and ew < 1e-3
+    assert pe < 0.5
+    assert sw[ok].sum() <= 1.1 * sc[ok].sum()
 
 
 def test_diverging_warm_start_falls_back_to_the_cold_start(U):
