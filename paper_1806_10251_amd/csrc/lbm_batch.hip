@@ -71,6 +71,10 @@ __device__ __forceinline__ int load_flag(const int* p) {
 constexpr int kInteriorBit = 30;
 constexpr int kTileMask = (1 << kInteriorBit) - 1;
 
+// Below this many active items the graph schedule launches one kernel per
+// step for all classes (kClsAny).
+constexpr long long kSplitMinItems = 2048;
+
 // Item classes of the graph schedule: each class is one launch per step, so
 // that each gets the registers of its own path (the interior path and the
 // closed-lattice boundary path fit eight blocks per compute unit; the outlet
@@ -350,6 +354,7 @@ struct lbm_batch {
   int n_items = 0, item_cap = 0;
   int cls_off[kNumClasses + 1] = {0, 0, 0, 0, 0};  // graph schedule: items of class k
                                                    // are [cls_off[k], cls_off[k + 1])
+  bool merged = false;  // graph schedule with few items: one launch per step
   double* d_partials = nullptr;
   double* d_case_res = nullptr;
   int* d_active = nullptr;
@@ -484,7 +489,16 @@ int rebuild_items(lbm_batch* b) {
       closed = closed && (sd[q] == LBM_SIDE_WALL || sd[q] == LBM_SIDE_LID);
     return int(closed ? kClsClosed : kClsOther);
   };
-  const int ncls = b->schedule == 2 ? 1 : kNumClasses;
+  // Few items (less than about two rounds of resident blocks): one launch
+  // per step that decides the path per item.  Each launch then runs for
+  // little more than its start-up latency, and one launch instead of up to
+  // four per step is what counts (the tail of a steady run, where a few
+  // cases remain).
+  long long active_items = 0;
+  for (int i = 0; i < b->n; ++i)
+    if (b->h_active[i]) active_items += b->cs[i].ntiles;
+  b->merged = b->schedule != 2 && active_items < kSplitMinItems;
+  const int ncls = (b->schedule == 2 || b->merged) ? 1 : kNumClasses;
   for (int k = 0; k < ncls; ++k) {
     b->cls_off[k] = (int)ic.size();
     auto take = [&](int i, int t) {
@@ -589,7 +603,8 @@ void launch_step_nts(int flavor, int cls, const StepLaunch& L, hipStream_t st) {
     case kClsInt: launch_step_cls<S, BY, NTS, kClsInt>(flavor, L, st); break;
     case kClsClosed: launch_step_cls<S, BY, NTS, kClsClosed>(flavor, L, st); break;
     case kClsOutlet: launch_step_cls<S, BY, NTS, kClsOutlet>(flavor, L, st); break;
-    default: launch_step_cls<S, BY, NTS, kClsOther>(flavor, L, st); break;
+    case kClsOther: launch_step_cls<S, BY, NTS, kClsOther>(flavor, L, st); break;
+    default: launch_step_cls<S, BY, NTS, kClsAny>(flavor, L, st); break;
   }
 }
 
@@ -652,6 +667,16 @@ void enqueue_window(lbm_batch* b, long long t, int nsteps, const RetireArgs& r, 
     const long long idx = (tt + 1) % b->K;
     const int flavor = idx == 0 ? kCheck : ((b->K >= 2 && idx == b->K - 1) ? kStore : kPlain);
     L.par = int(tt & 1);
+    if (b->merged) {
+      if (b->n_items > 0) {
+        if (b->storage == LBM_STORE_F64)
+          launch_step_storage<StoreF64>(b->by, flavor, kClsAny, nts, L, st);
+        else
+          launch_step_storage<StoreF32>(b->by, flavor, kClsAny, nts, L, st);
+      }
+      last_flavor = flavor;
+      continue;
+    }
     for (int k = 0; k < kNumClasses; ++k) {
       StepLaunch Lk = L;
       Lk.item_case = b->d_item_case + b->cls_off[k];

@@ -77,6 +77,44 @@ def test_batch_matches_single_lattice_runs(lbm, by, sched):
     b.close()
 
 
+def test_batch_per_class_launches_match_single_lattice_runs(lbm):
+    """With 2048 or more active items the graph schedule launches one kernel
+    per item class and step (interior tiles, closed-lattice boundary tiles,
+    outlet boundary tiles); with fewer, one kernel for all.  The small
+    batches above take the single launch; this one (2304 tiles of 64 x 4)
+    takes the per-class launches, and each case equals its single-lattice
+    run after the same 300 steps."""
+    rng = SplitMix64(77)
+    cases = []
+    for k in range(6):
+        cases.append(dict(nx=256, ny=256, sides=cavity_sides(),
+                          solid=random_obstacles(rng, 256, 256, "cavity") if k % 2 else None,
+                          kw=dict(nu=0.1 * 256 / (100 + 150 * k), gamma=0.3 + 0.1 * k,
+                                  u_lid=0.1)))
+        cases.append(dict(nx=512, ny=64, sides=channel_sides(),
+                          solid=random_obstacles(rng, 512, 64, "channel") if k % 2 else None,
+                          kw=dict(nu=0.05 * 64 / (20 + 10 * k), gamma=0.4 + 0.1 * k,
+                                  u_in_max=0.05)))
+    tiles = sum(-(-c["nx"] // 64) * -(-c["ny"] // 4) for c in cases)
+    assert tiles >= 2048
+    _say("per-class launches:", len(cases), "cases,", tiles, "tiles")
+    b = make_batch(lbm, cases)
+    b.set_launch(4, 0)
+    b.run(0.0, 300)
+    for i in (0, 1, 2, 3):
+        c = cases[i]
+        rb, uxb, uyb = b.fields(i, c["ny"], c["nx"])
+        g = lbm.Lattice(c["nx"], c["ny"], c["sides"], solid=c["solid"], storage="f32",
+                        check_every=100, **c["kw"])
+        g.step(300)
+        rs, uxs, uys = g.fields()
+        assert np.abs(uxb - uxs).max() < 1e-7, i
+        assert np.abs(uyb - uys).max() < 1e-7, i
+        assert np.abs(rb - rs).max() < 1e-6, i
+        g.close()
+    b.close()
+
+
 @pytest.mark.parametrize("sched,chunks", [(1, (300,)), (2, (300,)), (0, (130, 70, 100)),
                                           (2, (1, 149, 150))])
 def test_batch_schedules_and_partial_windows(lbm, sched, chunks):
