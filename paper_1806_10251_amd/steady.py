@@ -93,14 +93,20 @@ def batch_arm(cases, tol, max_steps, storage="f64", choice=None, warm_net=None, 
               plateau=(0, 0.9), segment=None, log=None):
     """One batched run of every case to tol from rest (or from the
     network's prediction, computed inside the timed region), with optional
-    filter steps.  segment: run in windows of that many steps (a multiple of
-    the check cadence), retiring finished cases between windows and logging
-    each window.  With the warm start, a predicted case that diverges is run
-    again from rest (the cold start is the fallback), inside the arm's time.
-    Returns (steps, status, seconds, [(ux, uy)] per case)."""
+    filter steps.  segment: run in windows of that many steps, retiring
+    finished cases between windows and logging each window.  With the warm
+    start the run always goes in windows (10 000 steps unless segment is
+    given): a predicted case that diverges is reset to rest inside the
+    running batch at the end of its window and runs again with the same
+    filter and a full step budget (the cold start is the fallback); its
+    steps include the failed attempt.  Returns (steps, status, seconds,
+    [(ux, uy)] per case)."""
     import torch
 
     from . import autotune, surrogate
+    n = len(cases)
+    if warm_net is not None and segment is None:
+        segment = 10_000
     grids = [L.make_grid(k.nx, k.ny, k.sides) for k in cases]
     params = [L.make_params(storage=storage, check_every=100, **case_kw(k)) for k in cases]
     b = L.Batch(grids, [k.mask for k in cases], params)
@@ -109,7 +115,7 @@ def batch_arm(cases, tol, max_steps, storage="f64", choice=None, warm_net=None, 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     if warm_net is not None:
-        surrogate.warm_init(warm_net, cases)(0, len(cases), b)
+        surrogate.warm_init(warm_net, cases)(0, n, b)
     done = 0
     for at in filter_at:
         b.run(0.0, at - done)
@@ -120,46 +126,72 @@ def batch_arm(cases, tol, max_steps, storage="f64", choice=None, warm_net=None, 
                                  plateau_checks=plateau[0], factor=plateau[1])
         total = np.where(st == 3, steps, steps + done)
     else:
-        n = len(cases)
+        taken = np.full(n, done, np.int64)      # steps each case has run in this arm
+        limit = np.full(n, max_steps, np.int64)
         total = np.full(n, -1, np.int64)
         st = np.zeros(n, np.int32)
         active = np.ones(n, bool)
-        while done < max_steps and active.any():
+        restarted = np.zeros(n, bool)
+        may_restart = np.array([warm_net is not None and surrogate.covers(k, warm_net)
+                                for k in cases])
+
+        def restart(idx):
+            # back to rest inside the batch, with the arm's filter steps
+            for i in idx:
+                b.init_fields(int(i))
+                restarted[i] = True
+                limit[i] = taken[i] + max_steps
+            en = np.zeros(n, np.int32)
+            en[idx] = 1
+            b.set_enabled(en)
+            d = 0
+            for at in filter_at:
+                b.run(0.0, at - d)
+                d = at
+                b.average_last_two()
+            taken[idx] += d
+            now = b.status() if filter_at else np.zeros(n, np.int32)
+            for i in idx:
+                if now[i] == 3:                  # diverges from rest as well
+                    total[i], st[i], active[i] = taken[i], 3, False
+            if log:
+                log(f"[tts] {len(idx)} warm-started case(s) diverged; reset to rest in the batch")
+
+        if warm_net is not None and filter_at:
+            now = b.status()
+            first = [i for i in range(n) if now[i] == 3 and may_restart[i]]
+            if first:
+                restart(np.array(first))
+        while True:
+            for i in np.flatnonzero(active):
+                if taken[i] >= limit[i]:
+                    total[i], st[i], active[i] = taken[i], 0, False
+            if not active.any():
+                break
+            m = int(min(segment, (limit - taken)[active].min()))
             b.set_enabled(active.astype(np.int32))
             b.set_plateau(*plateau)
-            m = min(segment, max_steps - done)
             steps = b.run(tol, m)
             now = b.status()
-            for i in range(n):
-                if active[i] and now[i] in (1, 2, 3):
-                    total[i] = done + abs(int(steps[i]))
-                    st[i] = now[i]
-                    active[i] = False
-            done += m
+            again = []
+            for i in np.flatnonzero(active):
+                if now[i] in (1, 2, 3):
+                    taken[i] += abs(int(steps[i]))
+                    if now[i] == 3 and may_restart[i] and not restarted[i]:
+                        again.append(i)
+                        continue
+                    total[i], st[i], active[i] = taken[i], now[i], False
+                else:
+                    taken[i] += m
+            if again:
+                restart(np.array(again))
             if log:
-                log(f"[tts] window to {done} steps: {int((~active).sum())}/{n} cases "
-                    f"retired, {time.perf_counter() - t0:.1f} s")
-        total[active] = done
+                log(f"[tts] window of {m} steps: {int((~active).sum())}/{n} cases retired, "
+                    f"{time.perf_counter() - t0:.1f} s")
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
     fields = [b.fields(i, k.ny, k.nx)[1:] for i, k in enumerate(cases)]
     b.close()
-    if warm_net is not None:
-        # the cold start is the fallback: a warm-started case that diverges
-        # runs again from rest (same filter); its steps and the time of the
-        # second run are added to the arm
-        redo = [i for i, k in enumerate(cases) if surrogate.covers(k, warm_net) and st[i] == 3]
-        if redo:
-            if log:
-                log(f"[tts] {len(redo)} warm-started case(s) diverged; rerun from rest")
-            steps2, st2, sec2, fields2 = batch_arm([cases[i] for i in redo], tol, max_steps,
-                                                   storage, choice, None, filter_at, plateau,
-                                                   segment, log)
-            for j, i in enumerate(redo):
-                total[i] += steps2[j]
-                st[i] = st2[j]
-                fields[i] = fields2[j]
-            sec += sec2
     return total, st, sec, fields
 
 
