@@ -177,12 +177,6 @@ def timed_window(warmup, steps, K):
             "check_every": K, "graph_windows": "captured graphs of K steps, replayed"}
 
 
-def _default_weights():
-    from paper_1806_10251_amd import surrogate
-    return surrogate.DEFAULT_WEIGHTS
-
-
-WEIGHTS = None   # set in time_to_steady (the library's default weights)
 
 
 def _case_kw(k):
@@ -231,12 +225,11 @@ def time_to_steady(lbm, n_cases, side_hi, max_steps, seed=1806, tol=1e-8):
                                       filter_at=surrogate.WARM_FILTER)
     arms["batch+filter@tol/10"] = _batch_arm(lbm, cases, choice, tol / 10, max_steps,
                                              filter_at=surrogate.WARM_FILTER)
-    global WEIGHTS
-    WEIGHTS = _default_weights()
+    weights = surrogate.DEFAULT_WEIGHTS
     net = None
-    if os.path.exists(WEIGHTS):
+    if os.path.exists(weights):
         net = U.UNet(max_batch=16, res=surrogate.RES, seed=0)
-        surrogate.load_into(net, WEIGHTS)
+        surrogate.load_into(net, weights)
         arms["batch+surrogate"] = _batch_arm(lbm, cases, choice, tol, max_steps, warm_net=net,
                                              filter_at=surrogate.WARM_FILTER)
         arms["batch+surrogate@tol/10"] = _batch_arm(lbm, cases, choice, tol / 10, max_steps,
@@ -281,7 +274,7 @@ def time_to_steady(lbm, n_cases, side_hi, max_steps, seed=1806, tol=1e-8):
                              "speedup_vs_plain": round(t_plain / sec, 3)}
     if net is not None:
         kinds = getattr(net, "kinds", ("cavity",))
-        out["warm_start"] = {"weights": os.path.relpath(WEIGHTS, ROOT),
+        out["warm_start"] = {"weights": os.path.relpath(weights, ROOT),
                              "covers": ", ".join(kinds) + " (other cases keep the cold start; a "
                                        "warm start that diverges runs again from rest within "
                                        "the arm)",
